@@ -1,0 +1,222 @@
+/*
+ * mfhex.h -- matrix-free high-order hexahedral operators on AMD MI355X (gfx950).
+ *
+ * C ABI of libmfhex.so.  The library applies the continuous-Galerkin mass and
+ * diffusion operators of tensor-product Q_p elements (Lagrange basis on
+ * Gauss-Lobatto points, reference element [-1,1]^3; Sec. 1) on structured
+ * hexahedral meshes, in the matrix-free factored form A^e = D^T G^e D with
+ * the six symmetric geometric factors G_rr ... G_tt stored per quadrature
+ * point (Sec. 2), by sum factorization, and solves with unpreconditioned CG.
+ * Benchmark problems (Sec. 1): mass = BP1, stiffness = BP3, collocated
+ * stiffness (Gauss-Lobatto quadrature at the nodes) = BP5; BP6 = BP5 with
+ * three components.
+ *
+ * Conventions shared by every call:
+ *   - Every function returns int: MFHEX_OK (0) or a negative MFHEX_ERR_*.
+ *     Nothing aborts or throws; mfhex_last_error() gives a message.
+ *   - "_dev" pointers are device (HBM) pointers owned by the CALLER; the
+ *     library never allocates or frees device memory.  Host pointers are
+ *     read during the call only.
+ *   - `stream` is a hipStream_t passed as void* (NULL = default stream).
+ *     apply / apply_adjoint / kappa_grad / rhs / *_coords enqueue work and
+ *     return without synchronizing.  create, cg and tune synchronize it.
+ *   - Node numbering: global node (I,J,K), I in [0, p*nex], is
+ *     I + (p*nex+1)*(J + (p*ney+1)*K).  Element (ex,ey,ez) is
+ *     ex + nex*(ey + ney*ez).  Quadrature point (a,b,c) of an element is
+ *     a + q*(b + q*c).
+ *   - Multi-vectors are row-major [n_nodes][nrhs][ncomp]: the nvec =
+ *     nrhs*ncomp values of a node are contiguous.  The operator acts on each
+ *     of the nvec columns independently (BP6 = three uncoupled components).
+ *   - With dirichlet = 1 the operator is M A M, M the 0/1 mask of interior
+ *     nodes: boundary entries of the input are ignored and those of the
+ *     output are zero.
+ *   - One handle must not be used from two host threads at once; distinct
+ *     handles are independent.
+ */
+#ifndef MFHEX_H
+#define MFHEX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+enum {
+    MFHEX_OK = 0,
+    MFHEX_ERR_ARG = -1,         /* invalid argument or size                      */
+    MFHEX_ERR_UNSUPPORTED = -2, /* valid but not built (e.g. p > 8)              */
+    MFHEX_ERR_HIP = -3,         /* a HIP runtime call failed                     */
+    MFHEX_ERR_MESH = -4,        /* an element has detJ <= 0 somewhere            */
+    MFHEX_ERR_NOCONV = -5,      /* CG reached maxit; x and stats are valid       */
+    MFHEX_ERR_BREAKDOWN = -6,   /* CG: p^T A p <= 0 or a non-finite value        */
+    MFHEX_ERR_STATE = -7        /* call not valid for this handle (e.g. no kappa) */
+};
+
+enum { MFHEX_MASS = 1, MFHEX_DIFFUSION = 2 };      /* operator kind       */
+enum { MFHEX_GAUSS = 0, MFHEX_GLL = 1 };           /* quadrature rule     */
+enum { MFHEX_F64 = 0, MFHEX_F32 = 1 };             /* arithmetic / data   */
+enum { MFHEX_CG_F64 = 0, MFHEX_CG_MIXED = 1 };     /* solver mode         */
+
+/* desc.flags bits */
+#define MFHEX_FLAG_F32 1u  /* also build FP32 quadrature data (for prec = MFHEX_F32) */
+#define MFHEX_FLAG_RHS 2u  /* keep w*detJ per point for mfhex_rhs on a diffusion op  */
+
+/* Operator description.
+ *   p in [1,8].  quad = MFHEX_GAUSS needs q = p+2 (mass and stiffness);
+ *   quad = MFHEX_GLL needs q = p+1 (collocated with the nodes).
+ *   kind: MFHEX_MASS (pointwise w*detJ) or MFHEX_DIFFUSION (pointwise
+ *   w adj(J) adj(J)^T / detJ, Sec. 2).  ncomp in {1,3}.
+ *   variable_kappa = 1 (diffusion, FP64 only): a per-point coefficient
+ *   set by mfhex_set_kappa multiplies the geometric factors.
+ *   vertex_xyz: HOST array [(nex+1)(ney+1)(nez+1)][3] of FP64 vertex
+ *   coordinates, x fastest; each hexahedron is the trilinear image of
+ *   [-1,1]^3 through its 8 vertices.  Copied into the workspace by create. */
+typedef struct {
+    int32_t nex, ney, nez;
+    int32_t p, q, quad, kind, ncomp, dirichlet, variable_kappa;
+    uint32_t flags;
+    const double *vertex_xyz;
+} mfhex_desc;
+
+/* Sizes derived from a description (filled by mfhex_query). */
+typedef struct {
+    int64_t n_nodes;        /* nodes per component, (p nex+1)(p ney+1)(p nez+1)     */
+    int64_t n_elem;         /* nex ney nez                                         */
+    int64_t n_qpts;         /* n_elem * q^3                                        */
+    size_t workspace_bytes; /* device workspace for mfhex_create                   */
+    size_t cg_work_bytes;   /* device work area for mfhex_cg (per solve, nrhs = 1) */
+} mfhex_sizes;
+
+typedef struct mfhex_op_s *mfhex_op; /* opaque; library-owned host state only */
+
+/* Validate `d` and compute sizes.  No device work. */
+int mfhex_query(const mfhex_desc *d, mfhex_sizes *out);
+
+/* Set up an operator: 1D bases on the host, element restriction (int32
+ * offsets, Dirichlet nodes encoded negative) copied into the workspace,
+ * quadrature data built on the GPU from the vertices (Sec. 2, the geometric
+ * factors G^e).  workspace_dev: caller-owned device buffer of at least
+ * sizes.workspace_bytes, 256-byte aligned, which must outlive the handle.
+ * Synchronizes `stream`.  Returns MFHEX_ERR_MESH if any point has
+ * detJ <= 0.  On error *out is NULL. */
+int mfhex_create(const mfhex_desc *d, void *workspace_dev, size_t workspace_bytes, void *stream,
+                 mfhex_op *out);
+
+/* Release the handle's host state.  Device memory stays with the caller. */
+int mfhex_destroy(mfhex_op op);
+
+/* Per-point coefficient kappa for a variable_kappa operator: device FP64
+ * [n_elem][q^3], copied into the workspace (asynchronous). */
+int mfhex_set_kappa(mfhex_op op, const double *kappa_dev, void *stream);
+
+/* y = A x for nvec = nrhs*ncomp columns, x and y device arrays of
+ * n_nodes*nvec FP64 (prec = MFHEX_F64) or FP32 (prec = MFHEX_F32, needs
+ * MFHEX_FLAG_F32; FP32 data and accumulation throughout).  y is fully
+ * overwritten.  x and y must not overlap.  Asynchronous.  (Sec. 2: the
+ * operator-level kernel w_L = A_L u_L, restriction, basis contractions,
+ * pointwise geometric factors and the transposes fused in one kernel.) */
+int mfhex_apply(mfhex_op op, int prec, int nrhs, const void *x_dev, void *y_dev, void *stream);
+
+/* y += A x (no zero fill of y); otherwise as mfhex_apply. */
+int mfhex_apply_add(mfhex_op op, int prec, int nrhs, const void *x_dev, void *y_dev, void *stream);
+
+/* y = A^T x.  The operators are symmetric, so this is the same action; it is
+ * the backward of mfhex_apply with respect to its input. */
+int mfhex_apply_adjoint(mfhex_op op, int prec, int nrhs, const void *x_dev, void *y_dev, void *stream);
+
+/* Gradient of s = r^T (M A(kappa) M) u with respect to the per-point
+ * coefficient: g[e][pt] = (Dhat M r)_pt^T G0_pt (Dhat M u)_pt, G0 the
+ * kappa-free geometric factors.  u, r: device FP64 [n_nodes] (ncomp = 1);
+ * g: device FP64 [n_elem][q^3], overwritten.  Diffusion operators only.
+ * For a loss L(y), r = dL/dy gives dL/dkappa.  Asynchronous. */
+int mfhex_kappa_grad(mfhex_op op, const double *u_dev, const double *r_dev, double *g_dev, void *stream);
+
+/* Physical coordinates of the quadrature points, device FP64
+ * [n_elem][q^3][3], and of the nodes, device FP64 [n_nodes][3] (for
+ * evaluating coefficients, forcings and nodal fields).  Asynchronous. */
+int mfhex_qpoint_coords(mfhex_op op, double *xyz_dev, void *stream);
+int mfhex_node_coords(mfhex_op op, double *xyz_dev, void *stream);
+
+/* Load vector b_n = sum over points of w detJ f phi_n (masked when
+ * dirichlet), f given per point as device FP64 [n_elem][q^3]; b: device
+ * FP64 [n_nodes], overwritten.  Mass operators, or diffusion operators
+ * created with MFHEX_FLAG_RHS.  Asynchronous. */
+int mfhex_rhs(mfhex_op op, const double *f_dev, double *b_dev, void *stream);
+
+/* CG options.
+ *   mode MFHEX_CG_F64: unpreconditioned Hestenes-Stiefel CG in FP64.
+ *   mode MFHEX_CG_MIXED: FP32 operator and FP32 r, p, Ap; FP64 x and all dot
+ *     products; the residual is replaced by the FP64 true residual
+ *     fp32(b - A64 x) whenever the recursive residual has fallen by
+ *     replace_delta since the last replacement, or every replace_every
+ *     iterations (needs MFHEX_FLAG_F32).
+ *   Stops when ||r||_2 <= rtol ||b||_2; in mixed mode only on the FP64 true
+ *   residual.  maxit bounds the iterations.  check_every: iterations
+ *   between host convergence checks (one stream sync each).  x0_is_zero = 0
+ *   starts from the given x.  max_iters_exact = 1 runs exactly maxit
+ *   iterations without convergence checks (FP64 mode; returns MFHEX_OK). */
+typedef struct {
+    int32_t maxit, check_every, mode, replace_every, x0_is_zero, max_iters_exact;
+    double rtol, replace_delta;
+} mfhex_cg_opts;
+
+typedef struct {
+    int32_t iters, replacements, fell_back_to_f64, pad_;
+    double rel_resid_true; /* ||b - A x|| / ||b|| in FP64 at exit          */
+    double rel_resid_rec;  /* recursive residual estimate at exit          */
+    double seconds;        /* wall time from first launch to exit          */
+} mfhex_cg_stats;
+
+/* Solve A x = b.  b, x: device FP64 [n_nodes] (ncomp = 1).  cg_work_dev:
+ * caller-owned device buffer of sizes.cg_work_bytes.  rhist (may be NULL):
+ * HOST array of maxit+1 doubles receiving ||r_k|| (recursive) after each
+ * iteration when check_every == 1 or max_iters_exact == 1.  Synchronizes
+ * `stream`.  Returns MFHEX_OK on convergence, MFHEX_ERR_NOCONV at maxit,
+ * MFHEX_ERR_BREAKDOWN on p^T A p <= 0 / non-finite values.  (Sec. 1: CG
+ * on the sum-factorized operator; Sec. 2: the benchmarks run it
+ * unpreconditioned.) */
+int mfhex_cg(mfhex_op op, const double *b_dev, double *x_dev, void *cg_work_dev, const mfhex_cg_opts *opts,
+             mfhex_cg_stats *stats, double *rhist, void *stream);
+
+/* Autotune the apply for (prec, nrhs): time every launch configuration
+ * (elements per block, thread layout) on this operator, reject any whose
+ * result differs from the default configuration by more than 1e-13
+ * (relative, max norm; 1e-5 for FP32), keep the fastest for this handle and
+ * append it to the text cache at cache_path (NULL: no file).  scratch_dev:
+ * caller-owned device buffer of at least MFHEX_TUNE_SCRATCH(n_nodes * nvec)
+ * bytes (256-byte aligned).
+ * Synchronizes `stream`. */
+#define MFHEX_TUNE_SCRATCH(len) (3 * ((((size_t)(len)) * 8 + 255) & ~(size_t)255) + 32768)
+int mfhex_tune(mfhex_op op, int prec, int nrhs, void *scratch_dev, const char *cache_path, void *stream);
+
+/* Elements per block the apply uses now for (prec, nrhs); 0 if unknown. */
+int mfhex_get_config(mfhex_op op, int prec, int nrhs, int32_t *elems_per_block);
+
+/* Force the elements-per-block configuration for (prec, nrhs) (testing and
+ * tuning); returns MFHEX_ERR_ARG if the value is not a valid candidate. */
+int mfhex_set_config(mfhex_op op, int prec, int nrhs, int32_t elems_per_block);
+
+/* Static message for a status code; message of the last failure on a
+ * handle (NULL op: last failure of a call that had no handle yet). */
+const char *mfhex_strerror(int code);
+const char *mfhex_last_error(mfhex_op op);
+
+/* The 1D data an operator of order p with rule (q, quad) uses, computed on
+ * the host (no device work): Gauss-Lobatto nodes [p+1], quadrature points and
+ * weights [q], interpolation B [q][p+1] (B[a][i] = l_i(x_a)) and the
+ * collocated derivative on the points D [q][q].  Any output may be NULL.
+ * (Sec. 1: Lagrange basis on Gauss-Lobatto points; Sec. 2: the dense 1D
+ * derivative matrix of the tensor contractions.) */
+int mfhex_basis_1d(int p, int q, int quad, double *nodes, double *xq, double *wq, double *B, double *D);
+
+/* Library version string. */
+const char *mfhex_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MFHEX_H */

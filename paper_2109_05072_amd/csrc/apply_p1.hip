@@ -1,0 +1,4 @@
+// Fused operator kernels of order p = 1 (one translation unit per order).
+#include "apply_kernels.hpp"
+
+MFHEX_DEFINE_ORDER(1)

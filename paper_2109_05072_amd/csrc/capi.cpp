@@ -1,0 +1,483 @@
+// C ABI of libmfhex: validation, workspace layout, operator setup and the
+// apply entry points.  Kernels live in the *.hip files; this file only checks
+// arguments, carves the caller's workspace and enqueues work on the caller's
+// stream.
+#include <climits>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <string>
+
+#include "blas.h"
+#include "op.h"
+
+using namespace mfhex;
+
+namespace {
+
+thread_local std::string g_err;  // last failure of a call that had no handle
+
+size_t al(size_t x) { return (x + 255) & ~size_t(255); }
+
+int fail(int code, const std::string &m)
+{
+    g_err = m;
+    return code;
+}
+
+int validate(const mfhex_desc *d, Basis1D *basis)
+{
+    if (!d) return fail(MFHEX_ERR_ARG, "null description");
+    if (d->nex < 1 || d->ney < 1 || d->nez < 1) return fail(MFHEX_ERR_ARG, "nex, ney, nez must be >= 1");
+    if (d->p < 1 || d->p > 8) return fail(MFHEX_ERR_UNSUPPORTED, "order p must be in [1, 8]");
+    if (d->kind != MFHEX_MASS && d->kind != MFHEX_DIFFUSION) return fail(MFHEX_ERR_ARG, "kind must be mass or diffusion");
+    if (d->ncomp != 1 && d->ncomp != 3) return fail(MFHEX_ERR_ARG, "ncomp must be 1 or 3");
+    if (d->dirichlet != 0 && d->dirichlet != 1) return fail(MFHEX_ERR_ARG, "dirichlet must be 0 or 1");
+    if (d->variable_kappa != 0 && d->variable_kappa != 1) return fail(MFHEX_ERR_ARG, "variable_kappa must be 0 or 1");
+    if (d->variable_kappa && d->kind != MFHEX_DIFFUSION)
+        return fail(MFHEX_ERR_ARG, "a variable coefficient needs a diffusion operator");
+    if (d->flags & ~(MFHEX_FLAG_F32 | MFHEX_FLAG_RHS)) return fail(MFHEX_ERR_ARG, "unknown flag bits");
+    if (!d->vertex_xyz) return fail(MFHEX_ERR_ARG, "vertex_xyz is null");
+    const int64_t N = (int64_t)(d->p * (int64_t)d->nex + 1) * (d->p * (int64_t)d->ney + 1) * (d->p * (int64_t)d->nez + 1);
+    if (N >= INT32_MAX) return fail(MFHEX_ERR_UNSUPPORTED, "more than 2^31-1 nodes (int32 restriction offsets)");
+    std::string e;
+    const int c = build_basis(d->p, d->q, d->quad, basis, &e);
+    if (c != MFHEX_OK) return fail(c, e);
+    return MFHEX_OK;
+}
+
+}  // namespace
+
+namespace mfhex {
+
+Layout workspace_layout(const mfhex_desc &d, int64_t E, int P, int Q)
+{
+    const int g = d.kind == MFHEX_DIFFUSION ? kQdDiff : 1;
+    const int64_t nv = (int64_t)(d.nex + 1) * (d.ney + 1) * (d.nez + 1);
+    const size_t Q3 = (size_t)Q * Q * Q, P3 = (size_t)P * P * P;
+    Layout L;
+    size_t o = 0;
+    L.vert = o;
+    o += al(nv * 3 * sizeof(double));
+    L.offsets = o;
+    o += al(E * P3 * sizeof(int32_t));
+    L.q64 = o;
+    o += al(E * g * Q3 * sizeof(double));
+    L.q32 = SIZE_MAX;
+    if (d.flags & MFHEX_FLAG_F32) {
+        L.q32 = o;
+        o += al(E * g * Q3 * sizeof(float));
+    }
+    L.kappa = SIZE_MAX;
+    if (d.variable_kappa) {
+        L.kappa = o;
+        o += al(E * Q3 * sizeof(double));
+    }
+    L.wdet = SIZE_MAX;
+    if ((d.flags & MFHEX_FLAG_RHS) && d.kind == MFHEX_DIFFUSION) {
+        L.wdet = o;
+        o += al(E * Q3 * sizeof(double));
+    }
+    L.bad = o;
+    o += 256;
+    L.total = o;
+    return L;
+}
+
+CgLayout cg_layout(int64_t n)
+{
+    CgLayout L;
+    size_t o = 0;
+    L.r64 = o;
+    o += al(n * 8);
+    L.p64 = o;
+    o += al(n * 8);
+    L.ap64 = o;
+    o += al(n * 8);
+    L.r32 = o;
+    o += al(n * 4);
+    L.p32 = o;
+    o += al(n * 4);
+    L.ap32 = o;
+    o += al(n * 4);
+    L.partial = o;
+    o += al(2 * kRedBlocks * 8);
+    L.sc = o;
+    o += al(kNumSc * 8);
+    L.hist = o;
+    o += al(kHist * 8);
+    L.total = o;
+    return L;
+}
+
+int set_error(mfhex_op op, int code, const std::string &msg)
+{
+    if (op) op->err = msg;
+    else g_err = msg;
+    return code;
+}
+
+int check_hip(mfhex_op op, hipError_t e, const char *what)
+{
+    if (e == hipSuccess) return MFHEX_OK;
+    return set_error(op, MFHEX_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+int mode_of(const mfhex_op_s &op) { return op.d.kind == MFHEX_DIFFUSION ? kDiff : kMass; }
+
+static size_t lds_bytes(const mfhex_op_s &op, int prec, int epb)
+{
+    const size_t s = prec == MFHEX_F32 ? 4 : 8;
+    return (size_t)epb * apply_nbuf(mode_of(op)) * lds_buf(op.Q) * s;
+}
+
+bool valid_epb(const mfhex_op_s &op, int prec, int epb)
+{
+    return epb >= 1 && epb * op.Q * op.Q <= kMaxThreads && lds_bytes(op, prec, epb) <= 65536;
+}
+
+int default_epb(const mfhex_op_s &op, int prec, int nvec)
+{
+    (void)nvec;
+    int e = 256 / (op.Q * op.Q);
+    if (e < 1) e = 1;
+    while (e > 1 && !valid_epb(op, prec, e)) --e;
+    return e;
+}
+
+int epb_for(const mfhex_op_s &op, int prec, int nvec)
+{
+    auto it = op.epb.find({prec, nvec});
+    if (it != op.epb.end()) return it->second;
+    return default_epb(op, prec, nvec);
+}
+
+hipError_t launch_apply(const ApplyLaunch &a)
+{
+    switch (a.basis->P - 1) {
+    case 1: return launch_apply_p1(a);
+    case 2: return launch_apply_p2(a);
+    case 3: return launch_apply_p3(a);
+    case 4: return launch_apply_p4(a);
+    case 5: return launch_apply_p5(a);
+    case 6: return launch_apply_p6(a);
+    case 7: return launch_apply_p7(a);
+    case 8: return launch_apply_p8(a);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_kgrad(const KgradLaunch &a)
+{
+    switch (a.basis->P - 1) {
+    case 1: return launch_kgrad_p1(a);
+    case 2: return launch_kgrad_p2(a);
+    case 3: return launch_kgrad_p3(a);
+    case 4: return launch_kgrad_p4(a);
+    case 5: return launch_kgrad_p5(a);
+    case 6: return launch_kgrad_p6(a);
+    case 7: return launch_kgrad_p7(a);
+    case 8: return launch_kgrad_p8(a);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+static OpView view_of(const mfhex_op_s &op, int prec)
+{
+    OpView v;
+    v.nelem = op.E;
+    v.nex = op.d.nex;
+    v.ney = op.d.ney;
+    v.nez = op.d.nez;
+    v.p = op.d.p;
+    v.q = op.d.q;
+    v.nnodes = op.N;
+    v.offsets = op.offsets;
+    v.qdata = prec == MFHEX_F32 ? (const void *)op.q32 : (const void *)op.q64;
+    v.kappa = op.kappa;
+    return v;
+}
+
+int apply_impl(mfhex_op op, int prec, int nrhs, const void *x, void *y, hipStream_t s, bool zero, int epb_override)
+{
+    if (!op) return set_error(nullptr, MFHEX_ERR_ARG, "null handle");
+    if (prec != MFHEX_F64 && prec != MFHEX_F32) return set_error(op, MFHEX_ERR_ARG, "prec must be F64 or F32");
+    if (nrhs < 1 || nrhs > 4096) return set_error(op, MFHEX_ERR_ARG, "nrhs must be in [1, 4096]");
+    if (!x || !y) return set_error(op, MFHEX_ERR_ARG, "null vector");
+    if (prec == MFHEX_F32 && !op->q32)
+        return set_error(op, MFHEX_ERR_STATE, "FP32 apply needs an operator created with MFHEX_FLAG_F32");
+    if (prec == MFHEX_F32 && op->d.variable_kappa)
+        return set_error(op, MFHEX_ERR_UNSUPPORTED, "variable coefficient is FP64 only");
+    if (op->d.variable_kappa && !op->kappa_set) return set_error(op, MFHEX_ERR_STATE, "kappa not set");
+    const int nvec = nrhs * op->d.ncomp;
+    const size_t bytes = (size_t)op->N * nvec * (prec == MFHEX_F32 ? 4 : 8);
+    const uintptr_t xa = (uintptr_t)x, ya = (uintptr_t)y;
+    if (xa < ya + bytes && ya < xa + bytes) return set_error(op, MFHEX_ERR_ARG, "x and y overlap");
+    const int epb = epb_override > 0 ? epb_override : epb_for(*op, prec, nvec);
+    if (!valid_epb(*op, prec, epb)) return set_error(op, MFHEX_ERR_ARG, "invalid elements-per-block");
+    if (zero) {
+        const int c = check_hip(op, hipMemsetAsync(y, 0, bytes, s), "hipMemsetAsync");
+        if (c) return c;
+    }
+    ApplyLaunch a{};
+    a.v = view_of(*op, prec);
+    a.basis = &op->basis;
+    a.prec = prec;
+    a.mode = mode_of(*op);
+    a.vark = op->d.variable_kappa;
+    a.nvec = nvec;
+    a.epb = epb;
+    a.x = x;
+    a.y = y;
+    a.wdet = nullptr;
+    a.stream = s;
+    return check_hip(op, launch_apply(a), "apply kernel launch");
+}
+
+}  // namespace mfhex
+
+// ---------------------------------------------------------------------------
+
+extern "C" {
+
+int mfhex_query(const mfhex_desc *d, mfhex_sizes *out)
+{
+    Basis1D b;
+    const int c = validate(d, &b);
+    if (c) return c;
+    if (!out) return fail(MFHEX_ERR_ARG, "null output");
+    const int P = d->p + 1, Q = d->q;
+    out->n_elem = (int64_t)d->nex * d->ney * d->nez;
+    out->n_nodes = (int64_t)(d->p * (int64_t)d->nex + 1) * (d->p * (int64_t)d->ney + 1) * (d->p * (int64_t)d->nez + 1);
+    out->n_qpts = out->n_elem * Q * Q * Q;
+    out->workspace_bytes = workspace_layout(*d, out->n_elem, P, Q).total;
+    out->cg_work_bytes = cg_layout(out->n_nodes).total;
+    return MFHEX_OK;
+}
+
+int mfhex_create(const mfhex_desc *d, void *workspace_dev, size_t workspace_bytes, void *stream, mfhex_op *out)
+{
+    if (!out) return fail(MFHEX_ERR_ARG, "null output handle");
+    *out = nullptr;
+    Basis1D b;
+    int c = validate(d, &b);
+    if (c) return c;
+    if (!workspace_dev || ((uintptr_t)workspace_dev & 255)) return fail(MFHEX_ERR_ARG, "workspace must be 256-byte aligned");
+    mfhex_op op = new mfhex_op_s();
+    op->d = *d;
+    op->d.vertex_xyz = nullptr;
+    op->basis = b;
+    op->P = d->p + 1;
+    op->Q = d->q;
+    op->g = d->kind == MFHEX_DIFFUSION ? kQdDiff : 1;
+    op->E = (int64_t)d->nex * d->ney * d->nez;
+    op->N = (int64_t)(d->p * (int64_t)d->nex + 1) * (d->p * (int64_t)d->ney + 1) * (d->p * (int64_t)d->nez + 1);
+    op->NQ = op->E * op->Q * op->Q * op->Q;
+    const Layout L = workspace_layout(*d, op->E, op->P, op->Q);
+    if (workspace_bytes < L.total) {
+        delete op;
+        return fail(MFHEX_ERR_ARG, "workspace too small (see mfhex_query)");
+    }
+    char *ws = static_cast<char *>(workspace_dev);
+    op->vert = reinterpret_cast<double *>(ws + L.vert);
+    op->offsets = reinterpret_cast<int32_t *>(ws + L.offsets);
+    op->q64 = reinterpret_cast<double *>(ws + L.q64);
+    op->q32 = L.q32 == SIZE_MAX ? nullptr : reinterpret_cast<float *>(ws + L.q32);
+    op->kappa = L.kappa == SIZE_MAX ? nullptr : reinterpret_cast<double *>(ws + L.kappa);
+    op->wdet = L.wdet == SIZE_MAX ? nullptr : reinterpret_cast<double *>(ws + L.wdet);
+    op->bad = reinterpret_cast<int32_t *>(ws + L.bad);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    auto bail = [&](int code) {
+        g_err = op->err;
+        if (op->pinned) (void)hipHostFree(op->pinned);
+        delete op;
+        return code;
+    };
+    if ((c = check_hip(op, hipGetDevice(&op->device), "hipGetDevice"))) return bail(c);
+    if ((c = check_hip(op, hipHostMalloc((void **)&op->pinned, 64 * sizeof(double)), "hipHostMalloc"))) return bail(c);
+    const int64_t nv = (int64_t)(d->nex + 1) * (d->ney + 1) * (d->nez + 1);
+    if ((c = check_hip(op, hipMemcpyAsync(op->vert, d->vertex_xyz, nv * 3 * sizeof(double), hipMemcpyHostToDevice, s),
+                       "copy vertices")))
+        return bail(c);
+    if ((c = check_hip(op, hipMemsetAsync(op->bad, 0, 256, s), "hipMemsetAsync"))) return bail(c);
+    GeomLaunch g{d->nex, d->ney, d->nez, d->p, d->q, op->vert, &op->basis, s};
+    if ((c = check_hip(op, launch_offsets(g, d->dirichlet, op->offsets), "offsets kernel"))) return bail(c);
+    if ((c = check_hip(op, launch_qdata(g, d->kind, op->q64, op->q32, op->wdet, op->bad), "qdata kernel")))
+        return bail(c);
+    if (op->kappa) {
+        if ((c = check_hip(op, hipMemsetAsync(op->kappa, 0, op->NQ * sizeof(double), s), "hipMemsetAsync")))
+            return bail(c);
+    }
+    int32_t bad = 0;
+    if ((c = check_hip(op, hipMemcpyAsync(&bad, op->bad, sizeof(int32_t), hipMemcpyDeviceToHost, s), "copy flag")))
+        return bail(c);
+    if ((c = check_hip(op, hipStreamSynchronize(s), "hipStreamSynchronize"))) return bail(c);
+    if (bad) {
+        op->err = "mesh has an element with detJ <= 0 at a quadrature point";
+        return bail(MFHEX_ERR_MESH);
+    }
+    load_tune_cache(op);
+    *out = op;
+    return MFHEX_OK;
+}
+
+int mfhex_destroy(mfhex_op op)
+{
+    if (!op) return MFHEX_OK;
+    if (op->pinned) (void)hipHostFree(op->pinned);
+    delete op;
+    return MFHEX_OK;
+}
+
+int mfhex_set_kappa(mfhex_op op, const double *kappa_dev, void *stream)
+{
+    if (!op) return fail(MFHEX_ERR_ARG, "null handle");
+    if (!op->d.variable_kappa || !op->kappa) return set_error(op, MFHEX_ERR_STATE, "operator has no variable coefficient");
+    if (!kappa_dev) return set_error(op, MFHEX_ERR_ARG, "null kappa");
+    const int c = check_hip(op, hipMemcpyAsync(op->kappa, kappa_dev, op->NQ * sizeof(double), hipMemcpyDeviceToDevice,
+                                               static_cast<hipStream_t>(stream)),
+                            "copy kappa");
+    if (c) return c;
+    op->kappa_set = true;
+    return MFHEX_OK;
+}
+
+int mfhex_apply(mfhex_op op, int prec, int nrhs, const void *x_dev, void *y_dev, void *stream)
+{
+    return apply_impl(op, prec, nrhs, x_dev, y_dev, static_cast<hipStream_t>(stream), true, 0);
+}
+
+int mfhex_apply_add(mfhex_op op, int prec, int nrhs, const void *x_dev, void *y_dev, void *stream)
+{
+    return apply_impl(op, prec, nrhs, x_dev, y_dev, static_cast<hipStream_t>(stream), false, 0);
+}
+
+int mfhex_apply_adjoint(mfhex_op op, int prec, int nrhs, const void *x_dev, void *y_dev, void *stream)
+{
+    // The mass and diffusion operators (and M A M) are symmetric.
+    return apply_impl(op, prec, nrhs, x_dev, y_dev, static_cast<hipStream_t>(stream), true, 0);
+}
+
+int mfhex_kappa_grad(mfhex_op op, const double *u_dev, const double *r_dev, double *g_dev, void *stream)
+{
+    if (!op) return fail(MFHEX_ERR_ARG, "null handle");
+    if (op->d.kind != MFHEX_DIFFUSION) return set_error(op, MFHEX_ERR_STATE, "coefficient gradient needs a diffusion operator");
+    if (op->d.ncomp != 1) return set_error(op, MFHEX_ERR_UNSUPPORTED, "coefficient gradient needs ncomp = 1");
+    if (!u_dev || !r_dev || !g_dev) return set_error(op, MFHEX_ERR_ARG, "null vector");
+    KgradLaunch a{};
+    a.v = view_of(*op, MFHEX_F64);
+    a.basis = &op->basis;
+    a.epb = epb_for(*op, MFHEX_F64, 1);
+    a.u = u_dev;
+    a.r = r_dev;
+    a.g = g_dev;
+    a.stream = static_cast<hipStream_t>(stream);
+    return check_hip(op, launch_kgrad(a), "coefficient gradient kernel launch");
+}
+
+int mfhex_qpoint_coords(mfhex_op op, double *xyz_dev, void *stream)
+{
+    if (!op) return fail(MFHEX_ERR_ARG, "null handle");
+    if (!xyz_dev) return set_error(op, MFHEX_ERR_ARG, "null output");
+    GeomLaunch g{op->d.nex, op->d.ney, op->d.nez, op->d.p, op->d.q, op->vert, &op->basis, static_cast<hipStream_t>(stream)};
+    return check_hip(op, launch_qpoint_coords(g, xyz_dev), "coordinates kernel");
+}
+
+int mfhex_node_coords(mfhex_op op, double *xyz_dev, void *stream)
+{
+    if (!op) return fail(MFHEX_ERR_ARG, "null handle");
+    if (!xyz_dev) return set_error(op, MFHEX_ERR_ARG, "null output");
+    GeomLaunch g{op->d.nex, op->d.ney, op->d.nez, op->d.p, op->d.q, op->vert, &op->basis, static_cast<hipStream_t>(stream)};
+    return check_hip(op, launch_node_coords(g, xyz_dev), "coordinates kernel");
+}
+
+int mfhex_rhs(mfhex_op op, const double *f_dev, double *b_dev, void *stream)
+{
+    if (!op) return fail(MFHEX_ERR_ARG, "null handle");
+    if (!f_dev || !b_dev) return set_error(op, MFHEX_ERR_ARG, "null vector");
+    const double *wdet = op->d.kind == MFHEX_MASS ? op->q64 : op->wdet;
+    if (!wdet) return set_error(op, MFHEX_ERR_STATE, "load vector needs a mass operator or MFHEX_FLAG_RHS");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    int c = check_hip(op, hipMemsetAsync(b_dev, 0, op->N * sizeof(double), s), "hipMemsetAsync");
+    if (c) return c;
+    ApplyLaunch a{};
+    a.v = view_of(*op, MFHEX_F64);
+    a.basis = &op->basis;
+    a.prec = MFHEX_F64;
+    a.mode = kRhs;
+    a.vark = 0;
+    a.nvec = 1;
+    a.epb = default_epb(*op, MFHEX_F64, 1);
+    // the load-vector kernel uses a single LDS buffer per element
+    a.x = f_dev;
+    a.y = b_dev;
+    a.wdet = wdet;
+    a.stream = s;
+    return check_hip(op, launch_apply(a), "load vector kernel launch");
+}
+
+int mfhex_cg(mfhex_op op, const double *b_dev, double *x_dev, void *cg_work_dev, const mfhex_cg_opts *opts,
+             mfhex_cg_stats *stats, double *rhist, void *stream)
+{
+    return cg_solve(op, b_dev, x_dev, cg_work_dev, opts, stats, rhist, static_cast<hipStream_t>(stream));
+}
+
+int mfhex_tune(mfhex_op op, int prec, int nrhs, void *scratch_dev, const char *cache_path, void *stream)
+{
+    return tune(op, prec, nrhs, scratch_dev, cache_path, static_cast<hipStream_t>(stream));
+}
+
+int mfhex_get_config(mfhex_op op, int prec, int nrhs, int32_t *elems_per_block)
+{
+    if (!op || !elems_per_block || nrhs < 1) return fail(MFHEX_ERR_ARG, "bad argument");
+    *elems_per_block = epb_for(*op, prec, nrhs * op->d.ncomp);
+    return MFHEX_OK;
+}
+
+int mfhex_set_config(mfhex_op op, int prec, int nrhs, int32_t elems_per_block)
+{
+    if (!op || nrhs < 1) return fail(MFHEX_ERR_ARG, "bad argument");
+    if (!valid_epb(*op, prec, elems_per_block)) return set_error(op, MFHEX_ERR_ARG, "invalid elements-per-block");
+    op->epb[{prec, nrhs * op->d.ncomp}] = elems_per_block;
+    return MFHEX_OK;
+}
+
+const char *mfhex_strerror(int code)
+{
+    switch (code) {
+    case MFHEX_OK: return "ok";
+    case MFHEX_ERR_ARG: return "invalid argument";
+    case MFHEX_ERR_UNSUPPORTED: return "unsupported configuration";
+    case MFHEX_ERR_HIP: return "HIP runtime error";
+    case MFHEX_ERR_MESH: return "inverted or degenerate element (detJ <= 0)";
+    case MFHEX_ERR_NOCONV: return "CG did not converge within maxit";
+    case MFHEX_ERR_BREAKDOWN: return "CG breakdown (p^T A p <= 0 or non-finite)";
+    case MFHEX_ERR_STATE: return "call not valid for this operator state";
+    default: return "unknown status";
+    }
+}
+
+const char *mfhex_last_error(mfhex_op op) { return op ? op->err.c_str() : g_err.c_str(); }
+
+int mfhex_basis_1d(int p, int q, int quad, double *nodes, double *xq, double *wq, double *B, double *D)
+{
+    Basis1D b;
+    std::string e;
+    const int c = build_basis(p, q, quad, &b, &e);
+    if (c) return fail(c, e);
+    for (int i = 0; i < b.P; ++i)
+        if (nodes) nodes[i] = b.nodes[i];
+    for (int a = 0; a < b.Q; ++a) {
+        if (xq) xq[a] = b.xq[a];
+        if (wq) wq[a] = b.wq[a];
+        for (int i = 0; i < b.P; ++i)
+            if (B) B[a * b.P + i] = b.B[a * b.P + i];
+        for (int k = 0; k < b.Q; ++k)
+            if (D) D[a * b.Q + k] = b.D[a * b.Q + k];
+    }
+    return MFHEX_OK;
+}
+
+const char *mfhex_version(void) { return "mfhex 0.1 (gfx950)"; }
+
+}  // extern "C"

@@ -1,0 +1,109 @@
+// Internal declarations shared by the host runtime (*.cpp) and the kernels (*.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "../../include/mfhex.h"
+
+namespace mfhex {
+
+constexpr int kMaxP = 9;   // nodes per direction (p = 8)
+constexpr int kMaxQ = 10;  // quadrature points per direction (q = p + 2)
+constexpr int kQdDiff = 6; // symmetric geometric factors per point (Voigt rr, ss, tt, st, rt, rs)
+constexpr int kNumXcd = 8; // MI355X: 8 accelerator complex dies, blocks dealt round-robin
+constexpr int kMaxThreads = 512;  // largest apply block (launch bound of the fused kernels)
+
+// 1D data of one operator, FP64 (host master copy) and FP32.
+struct Basis1D {
+    int P = 0, Q = 0;
+    bool colloc = false;             // Q == P and points == nodes (B = I)
+    double nodes[kMaxP];             // Gauss-Lobatto nodes
+    double xq[kMaxQ], wq[kMaxQ];     // quadrature points / weights
+    double B[kMaxQ * kMaxP];         // B[a*P + i] = l_i(xq_a)
+    double D[kMaxQ * kMaxQ];         // D[a*Q + b] = derivative at point a of the Lagrange
+                                     // polynomial through the points that is 1 at point b
+    double Gn[kMaxQ * kMaxP];        // Gn[a*P + i] = l_i'(xq_a)   (direct, for checks)
+};
+
+// Host side of the basis construction (basis.cpp).
+int build_basis(int p, int q, int quad, Basis1D *out, std::string *err);
+int gauss_rule(int n, double *x, double *w);
+int lobatto_rule(int n, double *x, double *w);
+
+// Kernel arguments common to the operator kernels.
+struct OpView {
+    int64_t nelem;
+    int32_t nex, ney, nez, p, q;
+    int64_t nnodes;
+    const int32_t *offsets;  // [E][P^3], -1 = masked node
+    const void *qdata;       // [E][g][Q^3] in the apply precision
+    const double *kappa;     // [E][Q^3] or null
+};
+
+enum Mode : int { kMass = 0, kDiff = 1, kRhs = 2 };
+
+struct ApplyLaunch {
+    OpView v;
+    const Basis1D *basis;
+    int prec;             // MFHEX_F64 / MFHEX_F32
+    int mode;             // kMass / kDiff / kRhs
+    int vark;             // multiply the factors by kappa
+    int nvec;
+    int epb;              // elements per block
+    const void *x;        // input (for kRhs: the per-point f, FP64)
+    void *y;              // output (accumulated)
+    const double *wdet;   // kRhs: w*detJ per point
+    hipStream_t stream;
+};
+
+struct KgradLaunch {
+    OpView v;
+    const Basis1D *basis;
+    int epb;
+    const double *u, *r;
+    double *g;
+    hipStream_t stream;
+};
+
+// LDS layout of one element's working array: [c][b][a] with an odd row pitch so
+// that pencils along any axis hit distinct banks.
+constexpr int lds_pitch(int Q) { return (Q % 2 == 0) ? Q + 1 : Q; }
+constexpr int lds_buf(int Q) { return lds_pitch(Q) * Q * Q; }
+constexpr int apply_nbuf(int mode) { return mode == 1 ? 3 : 1; }
+
+// Per-order dispatch (one translation unit per order, apply_p<N>.hip).
+hipError_t launch_apply(const ApplyLaunch &a);
+hipError_t launch_kgrad(const KgradLaunch &a);
+
+#define MFHEX_DECLARE_ORDER(N)                                  \
+    hipError_t launch_apply_p##N(const ApplyLaunch &a);         \
+    hipError_t launch_kgrad_p##N(const KgradLaunch &a);
+MFHEX_DECLARE_ORDER(1)
+MFHEX_DECLARE_ORDER(2)
+MFHEX_DECLARE_ORDER(3)
+MFHEX_DECLARE_ORDER(4)
+MFHEX_DECLARE_ORDER(5)
+MFHEX_DECLARE_ORDER(6)
+MFHEX_DECLARE_ORDER(7)
+MFHEX_DECLARE_ORDER(8)
+
+// Setup kernels (setup.hip).
+struct GeomLaunch {
+    int32_t nex, ney, nez, p, q;
+    const double *vert;      // device copy of the vertices
+    const Basis1D *basis;
+    hipStream_t stream;
+};
+// Quadrature data: diffusion -> 6 factors w adj(J) adj(J)^T / detJ per point,
+// mass -> w detJ.  q32 (optional) gets the FP32 rounding, wdet (optional) w detJ.
+// bad gets a nonzero value if some detJ <= 0 (caller zeroes it first).
+hipError_t launch_qdata(const GeomLaunch &g, int kind, double *q64, float *q32, double *wdet, int32_t *bad);
+hipError_t launch_offsets(const GeomLaunch &g, int dirichlet, int32_t *off);
+hipError_t launch_qpoint_coords(const GeomLaunch &g, double *xyz);
+hipError_t launch_node_coords(const GeomLaunch &g, double *xyz);
+
+}  // namespace mfhex

@@ -1,0 +1,60 @@
+// Host state of one operator handle (library-owned; device memory belongs to the caller).
+#pragma once
+
+#include <map>
+#include <string>
+#include <utility>
+
+#include "mfhex_internal.h"
+
+struct mfhex_op_s {
+    mfhex_desc d{};           // copy of the description (vertex pointer cleared)
+    mfhex::Basis1D basis{};
+    int P = 0, Q = 0, g = 0;  // nodes / points per direction, factors per point
+    int64_t N = 0, E = 0, NQ = 0;
+    int device = 0;
+    // views into the caller's workspace
+    double *vert = nullptr;
+    int32_t *offsets = nullptr;
+    double *q64 = nullptr;
+    float *q32 = nullptr;
+    double *kappa = nullptr;
+    double *wdet = nullptr;
+    int32_t *bad = nullptr;
+    bool kappa_set = false;
+    std::map<std::pair<int, int>, int> epb;  // (prec, nvec) -> elements per block
+    std::string err;
+    double *pinned = nullptr;  // small pinned host buffer for solver scalars
+};
+
+namespace mfhex {
+
+// Workspace layout (byte offsets, 256-aligned); absent parts are SIZE_MAX.
+struct Layout {
+    size_t vert, offsets, q64, q32, kappa, wdet, bad, total;
+};
+Layout workspace_layout(const mfhex_desc &d, int64_t E, int P, int Q);
+
+// Solver work layout for n nodes.
+struct CgLayout {
+    size_t r64, p64, ap64, r32, p32, ap32, partial, sc, hist, total;
+};
+constexpr int kHist = 8192;
+CgLayout cg_layout(int64_t n);
+
+int set_error(mfhex_op op, int code, const std::string &msg);
+int check_hip(mfhex_op op, hipError_t e, const char *what);
+
+// Internal apply: y (+)= A x on `s` with an explicit configuration.
+int apply_impl(mfhex_op op, int prec, int nrhs, const void *x, void *y, hipStream_t s, bool zero, int epb_override);
+int default_epb(const mfhex_op_s &op, int prec, int nvec);
+bool valid_epb(const mfhex_op_s &op, int prec, int epb);
+int epb_for(const mfhex_op_s &op, int prec, int nvec);
+int mode_of(const mfhex_op_s &op);
+
+int cg_solve(mfhex_op op, const double *b, double *x, void *work, const mfhex_cg_opts *o, mfhex_cg_stats *st,
+             double *rhist, hipStream_t s);
+int tune(mfhex_op op, int prec, int nrhs, void *scratch, const char *cache_path, hipStream_t s);
+void load_tune_cache(mfhex_op op);
+
+}  // namespace mfhex

@@ -1,0 +1,190 @@
+"""Torch-facing wrapper of one matrix-free operator.
+
+PyTorch provides device memory and the stream; the operator itself (setup
+of the geometric factors, every apply, the coefficient gradient, the load
+vector and the CG solve) runs in libmfhex.so.  There is no fallback: if the
+library or a GPU is missing, construction raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass
+from typing import Optional
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+_KINDS = {"mass": L.MFHEX_MASS, "diffusion": L.MFHEX_DIFFUSION}
+_QUADS = {"gauss": L.MFHEX_GAUSS, "gll": L.MFHEX_GLL}
+
+
+def _stream() -> int:
+    return torch.cuda.current_stream().cuda_stream
+
+
+def _prec(dtype) -> int:
+    if dtype == torch.float64:
+        return L.MFHEX_F64
+    if dtype == torch.float32:
+        return L.MFHEX_F32
+    raise TypeError(f"unsupported dtype {dtype}")
+
+
+@dataclass
+class CGResult:
+    x: torch.Tensor
+    status: int
+    iters: int
+    replacements: int
+    fell_back_to_f64: bool
+    rel_resid_true: float
+    rel_resid_rec: float
+    seconds: float
+    history: np.ndarray
+
+
+class Operator:
+    """Mass or diffusion operator of order p on a structured hexahedral mesh.
+
+    ``vertices``: host float64 array [(nex+1)(ney+1)(nez+1), 3], x fastest.
+    ``quad``: "gauss" (q = p+2) or "gll" (q = p+1, collocated).
+    """
+
+    def __init__(self, nex: int, ney: int, nez: int, p: int, vertices: np.ndarray, kind: str = "diffusion",
+                 quad: str = "gauss", ncomp: int = 1, dirichlet: bool = True, variable_kappa: bool = False,
+                 f32: bool = False, rhs: bool = False, device: str = "cuda"):
+        L.load()
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU: the matrix-free operators run only on the HIP device")
+        self.device = torch.device(device)
+        q = p + 2 if quad == "gauss" else p + 1
+        self._vert = np.ascontiguousarray(vertices, dtype=np.float64)
+        flags = (L.MFHEX_FLAG_F32 if f32 else 0) | (L.MFHEX_FLAG_RHS if rhs else 0)
+        self.desc = L.mfhex_desc(nex, ney, nez, p, q, _QUADS[quad], _KINDS[kind], ncomp, int(dirichlet),
+                                 int(variable_kappa), flags, self._vert.ctypes.data_as(C.POINTER(C.c_double)))
+        self.sizes = L.mfhex_query(self.desc)
+        self.p, self.q, self.ncomp = p, q, ncomp
+        self.kind, self.quad = kind, quad
+        self.n_nodes = int(self.sizes.n_nodes)
+        self.n_elem = int(self.sizes.n_elem)
+        with torch.cuda.device(self.device):
+            self.workspace = torch.empty(int(self.sizes.workspace_bytes) + 256, dtype=torch.uint8, device=self.device)
+            base = self.workspace.data_ptr()
+            self._ws_ptr = (base + 255) & ~255
+            self.handle = L.mfhex_create(self.desc, self._ws_ptr, int(self.sizes.workspace_bytes), _stream())
+        self._cg_work = None
+
+    # -- lifecycle ---------------------------------------------------------------------------
+    def close(self):
+        if getattr(self, "handle", None):
+            L.mfhex_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- helpers -----------------------------------------------------------------------------
+    def _check_vec(self, t: torch.Tensor, nrhs: int):
+        if t.device.type != "cuda" or not t.is_contiguous():
+            raise ValueError("vectors must be contiguous device tensors")
+        if t.numel() != self.n_nodes * nrhs * self.ncomp:
+            raise ValueError(f"vector has {t.numel()} entries, expected {self.n_nodes * nrhs * self.ncomp}")
+
+    def _nrhs(self, x: torch.Tensor) -> int:
+        per = self.n_nodes * self.ncomp
+        if x.numel() % per:
+            raise ValueError("vector length is not a multiple of n_nodes * ncomp")
+        return x.numel() // per
+
+    # -- operator actions --------------------------------------------------------------------
+    def apply(self, x: torch.Tensor, y: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """y = A x (x: [N], [N, ncomp] or [N, nrhs, ncomp]; float64 or float32)."""
+        nrhs = self._nrhs(x)
+        y = torch.empty_like(x) if y is None else y
+        self._check_vec(x, nrhs)
+        self._check_vec(y, nrhs)
+        L.mfhex_apply(self.handle, _prec(x.dtype), nrhs, x.data_ptr(), y.data_ptr(), _stream())
+        return y
+
+    def apply_add(self, x: torch.Tensor, y: torch.Tensor) -> torch.Tensor:
+        nrhs = self._nrhs(x)
+        self._check_vec(x, nrhs)
+        self._check_vec(y, nrhs)
+        L.mfhex_apply_add(self.handle, _prec(x.dtype), nrhs, x.data_ptr(), y.data_ptr(), _stream())
+        return y
+
+    def apply_adjoint(self, x: torch.Tensor, y: Optional[torch.Tensor] = None) -> torch.Tensor:
+        nrhs = self._nrhs(x)
+        y = torch.empty_like(x) if y is None else y
+        self._check_vec(x, nrhs)
+        self._check_vec(y, nrhs)
+        L.mfhex_apply_adjoint(self.handle, _prec(x.dtype), nrhs, x.data_ptr(), y.data_ptr(), _stream())
+        return y
+
+    def set_kappa(self, kappa: torch.Tensor) -> None:
+        kappa = kappa.contiguous()
+        if kappa.dtype != torch.float64 or kappa.numel() != self.n_elem * self.q ** 3:
+            raise ValueError("kappa must be float64 with n_elem * q^3 entries")
+        L.mfhex_set_kappa(self.handle, kappa.data_ptr(), _stream())
+
+    def kappa_grad(self, u: torch.Tensor, r: torch.Tensor) -> torch.Tensor:
+        """g[e, pt] = d(r^T A(kappa) u)/d kappa[e, pt]."""
+        self._check_vec(u, 1)
+        self._check_vec(r, 1)
+        g = torch.empty(self.n_elem, self.q ** 3, dtype=torch.float64, device=u.device)
+        L.mfhex_kappa_grad(self.handle, u.data_ptr(), r.data_ptr(), g.data_ptr(), _stream())
+        return g
+
+    def qpoint_coords(self) -> torch.Tensor:
+        xyz = torch.empty(self.n_elem, self.q ** 3, 3, dtype=torch.float64, device=self.device)
+        L.mfhex_qpoint_coords(self.handle, xyz.data_ptr(), _stream())
+        return xyz
+
+    def node_coords(self) -> torch.Tensor:
+        xyz = torch.empty(self.n_nodes, 3, dtype=torch.float64, device=self.device)
+        L.mfhex_node_coords(self.handle, xyz.data_ptr(), _stream())
+        return xyz
+
+    def rhs(self, f_q: torch.Tensor) -> torch.Tensor:
+        """Load vector of a per-point forcing f_q [n_elem, q^3] (masked when Dirichlet)."""
+        f_q = f_q.contiguous()
+        b = torch.empty(self.n_nodes, dtype=torch.float64, device=f_q.device)
+        L.mfhex_rhs(self.handle, f_q.data_ptr(), b.data_ptr(), _stream())
+        return b
+
+    # -- solver ------------------------------------------------------------------------------
+    def cg(self, b: torch.Tensor, x: Optional[torch.Tensor] = None, maxit: int = 1000, rtol: float = 1e-10,
+           mode: str = "f64", check_every: int = 1, replace_every: int = 100, replace_delta: float = 0.1,
+           exact_iters: bool = False) -> CGResult:
+        self._check_vec(b, 1)
+        if self._cg_work is None:
+            self._cg_work = torch.empty(int(self.sizes.cg_work_bytes) + 256, dtype=torch.uint8, device=self.device)
+        work = (self._cg_work.data_ptr() + 255) & ~255
+        x0_zero = x is None
+        x = torch.zeros_like(b) if x is None else x
+        opts = L.mfhex_cg_opts(maxit, check_every, L.MFHEX_CG_MIXED if mode == "mixed" else L.MFHEX_CG_F64,
+                               replace_every, int(x0_zero), int(exact_iters), rtol, replace_delta)
+        hist = np.zeros(min(maxit, 8191) + 1)
+        code, st = L.mfhex_cg(self.handle, b.data_ptr(), x.data_ptr(), work, opts,
+                              hist.ctypes.data_as(C.POINTER(C.c_double)), _stream())
+        return CGResult(x, code, st.iters, st.replacements, bool(st.fell_back_to_f64), st.rel_resid_true,
+                        st.rel_resid_rec, st.seconds, hist[: min(st.iters, 8191) + 1])
+
+    # -- tuning ------------------------------------------------------------------------------
+    def tune(self, dtype=torch.float64, nrhs: int = 1, cache_path: Optional[str] = None) -> int:
+        n = self.n_nodes * nrhs * self.ncomp
+        scratch = torch.empty(L.tune_scratch_bytes(n) + 256, dtype=torch.uint8, device=self.device)
+        ptr = (scratch.data_ptr() + 255) & ~255
+        L.mfhex_tune(self.handle, _prec(dtype), nrhs, ptr, cache_path, _stream())
+        return self.get_config(dtype, nrhs)
+
+    def get_config(self, dtype=torch.float64, nrhs: int = 1) -> int:
+        return L.mfhex_get_config(self.handle, _prec(dtype), nrhs)
+
+    def set_config(self, elems_per_block: int, dtype=torch.float64, nrhs: int = 1) -> None:
+        L.mfhex_set_config(self.handle, _prec(dtype), nrhs, elems_per_block)

@@ -1,0 +1,397 @@
+"""GPU parity: the HIP library, called through its C ABI, against the FP64 CPU
+oracle on the same seeded inputs.
+
+Tolerances (max-norm relative, ||y_gpu - y_orc||_inf / ||y_orc||_inf):
+  FP64 apply / load vector / coefficient gradient: 1e-12 (the stated target);
+  FP32 apply: 2e-5 (unit roundoff 6e-8 times the ~(3(p+q)+15)-term chains of
+  the contractions, with margin).
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12
+TOL32 = 2e-5
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+
+
+def relerr(a, b):
+    a = np.asarray(a)
+    b = np.asarray(b)
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def build(mf, nex, ney, nez, p, kind="diffusion", quad="gauss", dirichlet=True, ncomp=1, vark=False, f32=False,
+          rhs=False, perturb=0.1):
+    vert = synth.mesh_vertices(nex, ney, nez, perturb)
+    op = mf.Operator(nex, ney, nez, p, vert, kind=kind, quad=quad, ncomp=ncomp, dirichlet=dirichlet,
+                     variable_kappa=vark, f32=f32, rhs=rhs)
+    q = p + 2 if quad == "gauss" else p + 1
+    pr = oracle.Problem(nex, ney, nez, p, q, oracle.GAUSS if quad == "gauss" else oracle.GLL,
+                        oracle.DIFFUSION if kind == "diffusion" else oracle.MASS, int(dirichlet), vert)
+    return op, pr
+
+
+def interior_mask(pr):
+    nx, ny, nz = pr.p * pr.nex + 1, pr.p * pr.ney + 1, pr.p * pr.nez + 1
+    I = np.arange(pr.n_nodes)
+    ix, iy, iz = I % nx, (I // nx) % ny, I // (nx * ny)
+    return ((ix > 0) & (ix < nx - 1) & (iy > 0) & (iy < ny - 1) & (iz > 0) & (iz < nz - 1)).astype(float)
+
+
+def dev(a, dtype=torch.float64):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda", dtype)
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.double().cpu().numpy()
+
+
+def ragged_epb(op, dtype=torch.float64):
+    """A valid elements-per-block that does not divide the element count."""
+    from paper_2109_05072_amd import _lib as L
+    best = None
+    for e in range(2, 65):
+        try:
+            op.set_config(e, dtype)
+        except L.MFHexError:
+            continue
+        if op.n_elem % e and op.n_elem > e:
+            best = e
+    if best:
+        op.set_config(best, dtype)
+    return best
+
+
+# --- apply parity across orders, rules, masks ------------------------------------------------
+
+@pytest.mark.parametrize("p", range(1, 9))
+@pytest.mark.parametrize("kind,quad", [("diffusion", "gauss"), ("diffusion", "gll"), ("mass", "gauss")])
+@pytest.mark.parametrize("dirichlet", [True, False])
+def test_apply_fp64_matches_oracle(gpu_lib, p, kind, quad, dirichlet):
+    _say("apply64", p, kind, quad, dirichlet)
+    op, pr = build(gpu_lib, 5, 3, 2, p, kind, quad, dirichlet)
+    x = synth.uniform_vector(pr.n_nodes)
+    yo = oracle.apply(pr, x)
+    y = host(op.apply(dev(x)))
+    assert relerr(y, yo) <= TOL64
+    e = ragged_epb(op)
+    if e:
+        _say("apply64 ragged epb", e)
+        y2 = host(op.apply(dev(x)))
+        assert relerr(y2, yo) <= TOL64
+
+
+@pytest.mark.parametrize("p", [1, 3, 5, 8])
+@pytest.mark.parametrize("kind,quad", [("diffusion", "gauss"), ("diffusion", "gll"), ("mass", "gauss")])
+def test_apply_fp32_matches_oracle(gpu_lib, p, kind, quad):
+    _say("apply32", p, kind, quad)
+    op, pr = build(gpu_lib, 4, 3, 2, p, kind, quad, True, f32=True)
+    x = synth.uniform_vector(pr.n_nodes)
+    yo = oracle.apply(pr, x)
+    y = host(op.apply(dev(x, torch.float32)))
+    assert relerr(y, yo) <= TOL32
+
+
+@pytest.mark.parametrize("p,ncomp,nrhs", [(2, 3, 1), (3, 1, 4), (5, 3, 2), (8, 1, 3), (4, 3, 8)])
+@pytest.mark.parametrize("quad", ["gauss", "gll"])
+def test_multivector_matches_oracle_and_looped(gpu_lib, p, ncomp, nrhs, quad):
+    _say("multivector", p, ncomp, nrhs, quad)
+    op, pr = build(gpu_lib, 3, 3, 2, p, "diffusion", quad, True, ncomp=ncomp)
+    nvec = ncomp * nrhs
+    x = synth.uniform_vector(pr.n_nodes, nvec=nvec)
+    yo = oracle.apply(pr, x)
+    y = host(op.apply(dev(x)))
+    assert relerr(y, yo) <= TOL64
+    # one launch for all vectors == separate single-vector launches
+    if ncomp == 1:
+        single, _ = build(gpu_lib, 3, 3, 2, p, "diffusion", quad, True)
+        for v in range(nvec):
+            yv = host(single.apply(dev(x[:, v].copy())))
+            assert relerr(y[:, v], yv) <= 1e-14
+
+
+def test_apply_add_accumulates(gpu_lib):
+    op, pr = build(gpu_lib, 3, 2, 2, 3)
+    x = synth.uniform_vector(pr.n_nodes)
+    y0 = synth.uniform_vector(pr.n_nodes, seed=3)
+    y = dev(y0)
+    op.apply_add(dev(x), y)
+    assert relerr(host(y) - y0, oracle.apply(pr, x)) <= TOL64
+
+
+def test_adjoint_is_the_apply(gpu_lib):
+    op, pr = build(gpu_lib, 3, 2, 2, 4)
+    u = synth.uniform_vector(pr.n_nodes, seed=1)
+    v = synth.uniform_vector(pr.n_nodes, seed=2)
+    Au = host(op.apply(dev(u)))
+    ATv = host(op.apply_adjoint(dev(v)))
+    assert abs(v @ Au - u @ ATv) <= 1e-13 * np.linalg.norm(v) * np.linalg.norm(Au)
+
+
+# --- setup outputs --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("p,quad", [(2, "gauss"), (5, "gll")])
+def test_coordinates_match_oracle(gpu_lib, p, quad):
+    op, pr = build(gpu_lib, 3, 2, 4, p, "diffusion", quad)
+    xq, _ = oracle.qpoint_geometry(pr)
+    assert np.abs(host(op.qpoint_coords()) - xq).max() <= 1e-15
+    assert np.abs(host(op.node_coords()) - oracle.node_coords(pr)).max() <= 1e-15
+
+
+@pytest.mark.parametrize("p,kind", [(2, "mass"), (4, "diffusion"), (7, "diffusion")])
+def test_load_vector_matches_oracle(gpu_lib, p, kind):
+    op, pr = build(gpu_lib, 3, 3, 2, p, kind, "gauss", dirichlet=(kind == "diffusion"), rhs=True)
+    f = synth.sin_forcing(host(op.qpoint_coords()))
+    fo = synth.sin_forcing(oracle.qpoint_geometry(pr)[0])
+    b = host(op.rhs(dev(f)))
+    assert relerr(b, oracle.rhs(pr, fo)) <= TOL64
+
+
+# --- invariants on the GPU at larger sizes -------------------------------------------------
+
+@pytest.mark.parametrize("p", [1, 3, 6])
+def test_gpu_invariants(gpu_lib, p):
+    ne = max(2, 24 // p)
+    opm, _ = build(gpu_lib, ne, ne, ne, p, "mass", "gauss", dirichlet=False)
+    one = torch.ones(opm.n_nodes, dtype=torch.float64, device="cuda")
+    assert abs(float(one @ opm.apply(one)) - 1.0) < 1e-12
+    opd, pr = build(gpu_lib, ne, ne, ne, p, "diffusion", "gauss", dirichlet=False)
+    X = opd.node_coords()
+    u = 0.4 + X @ torch.tensor([1.0, -2.0, 0.5], dtype=torch.float64, device="cuda")
+    y = host(opd.apply(u.contiguous()))
+    n = p * ne + 1
+    I = np.arange(opd.n_nodes)
+    ix, iy, iz = I % n, (I // n) % n, I // (n * n)
+    inner = (ix > 0) & (ix < n - 1) & (iy > 0) & (iy < n - 1) & (iz > 0) & (iz < n - 1)
+    assert np.abs(y[inner]).max() <= 1e-12 * np.abs(y).max()
+
+
+def test_run_to_run_spread(gpu_lib):
+    op, pr = build(gpu_lib, 8, 8, 8, 3)
+    x = dev(synth.uniform_vector(pr.n_nodes))
+    ys = [host(op.apply(x)) for _ in range(5)]
+    spread = max(relerr(y, ys[0]) for y in ys)
+    print("run-to-run spread", spread)
+    assert spread <= 1e-14
+
+
+# --- autotuner ------------------------------------------------------------------------------
+
+@pytest.mark.parametrize("p,quad,nrhs", [(3, "gauss", 1), (8, "gauss", 1), (5, "gll", 4)])
+def test_every_launch_configuration_agrees(gpu_lib, p, quad, nrhs):
+    from paper_2109_05072_amd import _lib as L
+    op, pr = build(gpu_lib, 4, 3, 3, p, "diffusion", quad)
+    x = dev(synth.uniform_vector(pr.n_nodes, nvec=nrhs))
+    ref = host(op.apply(x))
+    ok = 0
+    for e in range(1, 65):
+        try:
+            op.set_config(e, nrhs=nrhs)
+        except L.MFHexError:
+            continue
+        assert relerr(host(op.apply(x)), ref) <= 1e-13
+        ok += 1
+    assert ok >= 1
+    best = op.tune(nrhs=nrhs)
+    assert best >= 1
+    assert relerr(host(op.apply(x)), ref) <= 1e-13
+
+
+# --- coefficient gradient -------------------------------------------------------------------
+
+@pytest.mark.parametrize("p,quad", [(2, "gauss"), (4, "gauss"), (3, "gll")])
+def test_variable_kappa_apply_and_gradient_match_oracle(gpu_lib, p, quad):
+    op, pr = build(gpu_lib, 3, 3, 2, p, "diffusion", quad, True, vark=True)
+    kap = synth.kappa_field(host(op.qpoint_coords()))
+    kapo = synth.kappa_field(oracle.qpoint_geometry(pr)[0])
+    pr = pr.with_(kappa=kapo)
+    op.set_kappa(dev(kap))
+    u = synth.uniform_vector(pr.n_nodes, seed=1)
+    r = synth.uniform_vector(pr.n_nodes, seed=2)
+    assert relerr(host(op.apply(dev(u))), oracle.apply(pr, u)) <= TOL64
+    g = host(op.kappa_grad(dev(u), dev(r)))
+    assert relerr(g, oracle.kappa_grad(pr, u, r)) <= TOL64
+
+
+def test_autograd_gradients_vs_finite_differences_and_oracle(gpu_lib):
+    from paper_2109_05072_amd.autograd import diffusion
+    op, pr = build(gpu_lib, 3, 2, 2, 2, "diffusion", "gauss", True, vark=True)
+    kap = dev(synth.kappa_field(host(op.qpoint_coords())))
+    n = pr.n_nodes
+    u = dev(synth.uniform_vector(n, seed=1)).requires_grad_(True)
+    f = dev(synth.uniform_vector(n, seed=2))
+    k = kap.clone().requires_grad_(True)
+
+    def loss(uu, kk):
+        r = diffusion(uu, kk, op) - f
+        return 0.5 * (r * r).sum()
+
+    Lv = loss(u, k)
+    gu, gk = torch.autograd.grad(Lv, [u, k])
+    rng = np.random.default_rng(synth.SEED_DIR)
+    with torch.no_grad():
+        for _ in range(4):
+            d = dev(rng.standard_normal(kap.shape))
+            eps = 1e-2 * float(kap.norm() / d.norm())
+            fd = (loss(u, k + eps * d) - loss(u, k - eps * d)) / (2 * eps)
+            an = (gk * d).sum()
+            assert abs(float(fd - an)) <= 1e-9 * abs(float(an))
+            du = dev(rng.standard_normal(n))
+            eps = 1e-2 * float(u.norm() / du.norm())
+            fd = (loss(u + eps * du, k) - loss(u - eps * du, k)) / (2 * eps)
+            an = (gu * du).sum()
+            assert abs(float(fd - an)) <= 1e-9 * abs(float(an))
+    # against the oracle's gradient (its own coefficient and residual)
+    kapo = synth.kappa_field(oracle.qpoint_geometry(pr)[0])
+    pro = pr.with_(kappa=kapo)
+    uo = host(u.detach())
+    r = oracle.apply(pro, uo) - host(f)
+    assert relerr(host(gk), oracle.kappa_grad(pro, uo, r)) <= 1e-11
+    assert relerr(host(gu), oracle.apply(pro, r)) <= 1e-11
+
+
+def test_torch_gradcheck_tiny(gpu_lib):
+    from paper_2109_05072_amd.autograd import MFHexDiffusion
+    op, pr = build(gpu_lib, 2, 1, 1, 1, "diffusion", "gauss", False, vark=True)
+    kap = dev(synth.kappa_field(host(op.qpoint_coords()))).requires_grad_(True)
+    u = dev(synth.uniform_vector(pr.n_nodes)).requires_grad_(True)
+    assert torch.autograd.gradcheck(lambda a, b: MFHexDiffusion.apply(a, b, op), (u, kap), eps=1e-6, atol=1e-8)
+
+
+# --- CG -------------------------------------------------------------------------------------
+
+def test_config0_fifty_cg_iterations_match_oracle(gpu_lib):
+    # 4x4x4 perturbed mesh, p = 2, Gauss q = 4, Dirichlet, 50 iterations from x0 = 0
+    op, pr = build(gpu_lib, 4, 4, 4, 2)
+    assert op.n_nodes == 729
+    x = synth.uniform_vector(pr.n_nodes)
+    assert relerr(host(op.apply(dev(x))), oracle.apply(pr, x)) <= TOL64
+    b = synth.uniform_vector(pr.n_nodes, seed=3) * interior_mask(pr)
+    xo, ho, it, _ = oracle.cg(pr, b, maxit=50, rtol=0.0)
+    assert it == 50
+    res = op.cg(dev(b), maxit=50, rtol=0.0, exact_iters=True)
+    xg = host(res.x)
+    print("config0 x50 rel diff", relerr(xg, xo), "history max rel diff", relerr(res.history, ho))
+    assert res.iters == 50
+    assert relerr(xg, xo) <= 1e-10
+    assert np.all(np.abs(res.history - ho) <= 1e-10 * ho + 1e-14 * ho[0])
+
+
+def _masked_rhs(op, pr):
+    f = synth.sin_forcing(host(op.qpoint_coords()))
+    return op.rhs(dev(f))
+
+
+@pytest.mark.parametrize("p", [2, 3])
+def test_cg_solution_and_mixed_precision(gpu_lib, p):
+    ne = 12 if p == 2 else 8
+    op, pr = build(gpu_lib, ne, ne, ne, p, "diffusion", "gauss", True, f32=True, rhs=True)
+    b = _masked_rhs(op, pr)
+    r64 = op.cg(b, maxit=5000, rtol=1e-10, mode="f64")
+    rmx = op.cg(b, maxit=5000, rtol=1e-10, mode="mixed")
+    print("f64", r64.iters, r64.rel_resid_true, r64.seconds, "mixed", rmx.iters, rmx.replacements,
+          rmx.rel_resid_true, rmx.seconds, rmx.fell_back_to_f64)
+    assert r64.status == 0 and r64.rel_resid_true <= 1e-10
+    assert rmx.status == 0 and rmx.rel_resid_true <= 1e-10
+    x64, xmx = host(r64.x), host(rmx.x)
+    # against the oracle's own solve of its own load vector
+    fo = synth.sin_forcing(oracle.qpoint_geometry(pr)[0])
+    bo = oracle.rhs(pr, fo)
+    assert relerr(host(b), bo) <= TOL64
+    xo, _, _, _ = oracle.cg(pr, bo, maxit=5000, rtol=1e-12)
+    print("err f64 vs oracle", relerr(x64, xo), "err mixed vs oracle", relerr(xmx, xo))
+    assert relerr(x64, xo) <= 1e-7
+    assert relerr(xmx, xo) <= 1e-7
+    # discretization error against the exact solution is far above the solver error
+    ue = synth.sin_solution(host(op.node_coords()))
+    assert np.abs(x64 - ue).max() < 1e-2
+
+
+# --- error paths -----------------------------------------------------------------------------
+
+def test_error_paths(gpu_lib):
+    from paper_2109_05072_amd import _lib as L
+    vert = synth.mesh_vertices(3, 3, 3, perturb=0.7)
+    with pytest.raises(L.MFHexError) as ei:
+        gpu_lib.Operator(3, 3, 3, 2, vert)
+    assert ei.value.code == L.MFHEX_ERR_MESH
+    op, pr = build(gpu_lib, 2, 2, 2, 2)
+    x = dev(synth.uniform_vector(pr.n_nodes))
+    with pytest.raises(L.MFHexError) as ei:
+        op.apply(x.float())
+    assert ei.value.code == L.MFHEX_ERR_STATE
+    with pytest.raises(L.MFHexError) as ei:
+        L.mfhex_apply(op.handle, L.MFHEX_F64, 1, x.data_ptr(), x.data_ptr() + 8, 0)
+    assert ei.value.code == L.MFHEX_ERR_ARG
+    opk, _ = build(gpu_lib, 2, 2, 2, 2, vark=True)
+    with pytest.raises(L.MFHexError) as ei:
+        opk.apply(x)
+    assert ei.value.code == L.MFHEX_ERR_STATE
+    # one element, p = 1, Dirichlet: every node is on the boundary -> y = 0
+    op1, pr1 = build(gpu_lib, 1, 1, 1, 1)
+    y = host(op1.apply(dev(synth.uniform_vector(pr1.n_nodes))))
+    assert np.all(y == 0.0)
+
+
+# --- full-size, sampled against the oracle one output at a time -----------------------------
+
+def _window_value(vert_full, nex, ney, nez, p, quad, kind, dirichlet, x_full, node):
+    """(A x)[node] from the oracle on the <= 2x2x2 elements around the node."""
+    nx, ny = p * nex + 1, p * ney + 1
+    I, J, K = node % nx, (node // nx) % ny, node // (nx * ny)
+    lo, hi = [], []
+    for L_, ne in ((I, nex), (J, ney), (K, nez)):
+        a = max(0, (L_ - 1) // p) if L_ % p == 0 else L_ // p
+        b = min(ne - 1, L_ // p)
+        lo.append(a)
+        hi.append(b)
+    wx, wy, wz = hi[0] - lo[0] + 1, hi[1] - lo[1] + 1, hi[2] - lo[2] + 1
+    V = vert_full.reshape(nez + 1, ney + 1, nex + 1, 3)
+    wv = V[lo[2]:hi[2] + 2, lo[1]:hi[1] + 2, lo[0]:hi[0] + 2].reshape(-1, 3)
+    q = p + 2 if quad == oracle.GAUSS else p + 1
+    pr = oracle.Problem(wx, wy, wz, p, q, quad, kind, 0, np.ascontiguousarray(wv))
+    lnx, lny, lnz = p * wx + 1, p * wy + 1, p * wz + 1
+    gi = np.arange(lnx)[None, None, :] + p * lo[0]
+    gj = np.arange(lny)[None, :, None] + p * lo[1]
+    gk = np.arange(lnz)[:, None, None] + p * lo[2]
+    gid = (gi + nx * (gj + ny * gk)).reshape(-1)
+    xw = x_full[gid].copy()
+    if dirichlet:
+        Gi, Gj, Gk = gid % nx, (gid // nx) % ny, gid // (nx * ny)
+        bnd = (Gi == 0) | (Gi == nx - 1) | (Gj == 0) | (Gj == ny - 1) | (Gk == 0) | (Gk == p * nez)
+        xw[bnd] = 0.0
+    yw = oracle.apply(pr, xw)
+    li = (I - p * lo[0]) + lnx * ((J - p * lo[1]) + lny * (K - p * lo[2]))
+    return yw[li]
+
+
+@pytest.mark.parametrize("p", [3, 8])
+def test_full_size_sampled_against_oracle(gpu_lib, p):
+    ne = synth.elems_for_dofs(1e7, p)
+    _say("full size", p, ne)
+    op, _ = build(gpu_lib, ne, ne, ne, p, "diffusion", "gauss", True)
+    vert = synth.mesh_vertices(ne, ne, ne)
+    x = synth.uniform_vector(op.n_nodes)
+    y = host(op.apply(dev(x)))
+    rng = np.random.default_rng(17)
+    n = p * ne + 1
+    nodes = list(rng.integers(0, op.n_nodes, size=24))
+    nodes += [1 + n + n * n, (n - 2) + n * (n - 2) + n * n * (n - 2), p + n * p + n * n * p]  # near corners, vertex
+    scale = np.abs(y).max()
+    for node in nodes:
+        I, J, K = node % n, (node // n) % n, node // (n * n)
+        if min(I, J, K) == 0 or max(I, J, K) == n - 1:
+            assert y[node] == 0.0
+            continue
+        yo = _window_value(vert, ne, ne, ne, p, oracle.GAUSS, oracle.DIFFUSION, True, x, node)
+        assert abs(y[node] - yo) <= TOL64 * scale, (node, y[node], yo)
