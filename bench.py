@@ -104,7 +104,7 @@ def main():
         if args.tune:
             op.tune()
         meta[p] = dict(ne=ne, N=op.n_nodes, E=op.n_elem, q=p + 2, epb=op.get_config())
-        print(f"# setup p={p}: {ne}^3 elements, {op.n_nodes} DOFs, elements/block {meta[p]['epb']}",
+        print(f"# setup p={p}: {ne}^3 elements, {op.n_nodes} DOFs, launch (variant, elems, threads) {meta[p]['epb']}",
               file=sys.stderr, flush=True)
 
     for _ in range(args.warmup):
@@ -138,7 +138,8 @@ def main():
                       "gdofs": round(m["N"] / (t_ms / 1e3) / 1e9, 3), "alg_bytes": byts,
                       "alg_gbs": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
                       "alg_tflops": round(alg_flops(m["E"], p, m["q"]) / (t_ms / 1e3) / 1e12, 2),
-                      "elements_per_block": m["epb"],
+                      "launch": {"variant": m["epb"][0], "elements_per_group": m["epb"][1],
+                                 "threads_per_group": m["epb"][2]},
                       "paper_v100_cuda_gen_gdofs": PAPER_V100_CUDA_GEN.get(p)})
     dom = max(per_p, key=lambda r: r["ms"])
     out = {

@@ -181,23 +181,25 @@ typedef struct {
 int mfhex_cg(mfhex_op op, const double *b_dev, double *x_dev, void *cg_work_dev, const mfhex_cg_opts *opts,
              mfhex_cg_stats *stats, double *rhist, void *stream);
 
-/* Autotune the apply for (prec, nrhs): time every launch configuration
- * (elements per block, thread layout) on this operator, reject any whose
- * result differs from the default configuration by more than 1e-13
- * (relative, max norm; 1e-5 for FP32), keep the fastest for this handle and
- * append it to the text cache at cache_path (NULL: no file).  scratch_dev:
- * caller-owned device buffer of at least MFHEX_TUNE_SCRATCH(n_nodes * nvec)
- * bytes (256-byte aligned).
- * Synchronizes `stream`. */
+/* Autotune the apply for (prec, nrhs): time every launch variant of the
+ * fused kernel (elements per thread group, threads per group) on this
+ * operator, reject any whose result differs from the default variant by more
+ * than 1e-13 (relative, max norm; 1e-5 for FP32), keep the fastest for this
+ * handle and append "<arch> kind quad p nvec prec variant" to the text cache
+ * at cache_path (NULL: no file); handles created later read the file named by
+ * the environment variable MFHEX_TUNE_CACHE.  scratch_dev: caller-owned
+ * device buffer of at least MFHEX_TUNE_SCRATCH(n_nodes * nvec) bytes
+ * (256-byte aligned).  Synchronizes `stream`. */
 #define MFHEX_TUNE_SCRATCH(len) (3 * ((((size_t)(len)) * 8 + 255) & ~(size_t)255) + 32768)
 int mfhex_tune(mfhex_op op, int prec, int nrhs, void *scratch_dev, const char *cache_path, void *stream);
 
-/* Elements per block the apply uses now for (prec, nrhs); 0 if unknown. */
-int mfhex_get_config(mfhex_op op, int prec, int nrhs, int32_t *elems_per_block);
+/* Launch variant the apply uses now for (prec, nrhs), with the elements per
+ * thread group and threads per group it stands for (outputs may be NULL). */
+int mfhex_get_config(mfhex_op op, int prec, int nrhs, int32_t *variant, int32_t *elems_per_group,
+                     int32_t *threads_per_group);
 
-/* Force the elements-per-block configuration for (prec, nrhs) (testing and
- * tuning); returns MFHEX_ERR_ARG if the value is not a valid candidate. */
-int mfhex_set_config(mfhex_op op, int prec, int nrhs, int32_t elems_per_block);
+/* Force the launch variant (0 .. 2) for (prec, nrhs); MFHEX_ERR_ARG if out of range. */
+int mfhex_set_config(mfhex_op op, int prec, int nrhs, int32_t variant);
 
 /* Static message for a status code; message of the last failure on a
  * handle (NULL op: last failure of a call that had no handle yet). */

@@ -101,7 +101,8 @@ def load(path: str = LIB_PATH):
         "mfhex_cg": ([vp, vp, vp, vp, C.POINTER(mfhex_cg_opts), C.POINTER(mfhex_cg_stats),
                       C.POINTER(C.c_double), vp], i32),
         "mfhex_tune": ([vp, i32, i32, vp, C.c_char_p, vp], i32),
-        "mfhex_get_config": ([vp, i32, i32, C.POINTER(C.c_int32)], i32),
+        "mfhex_get_config": ([vp, i32, i32, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                              C.POINTER(C.c_int32)], i32),
         "mfhex_set_config": ([vp, i32, i32, C.c_int32], i32),
         "mfhex_strerror": ([i32], C.c_char_p),
         "mfhex_last_error": ([vp], C.c_char_p),
@@ -188,14 +189,15 @@ def mfhex_tune(op: int, prec: int, nrhs: int, scratch: int, cache_path, stream: 
     check(load().mfhex_tune(op, prec, nrhs, scratch, cp, stream), op)
 
 
-def mfhex_get_config(op: int, prec: int, nrhs: int) -> int:
-    v = C.c_int32()
-    check(load().mfhex_get_config(op, prec, nrhs, C.byref(v)), op)
-    return v.value
+def mfhex_get_config(op: int, prec: int, nrhs: int):
+    """(variant, elements per group, threads per group)."""
+    v, g, t = C.c_int32(), C.c_int32(), C.c_int32()
+    check(load().mfhex_get_config(op, prec, nrhs, C.byref(v), C.byref(g), C.byref(t)), op)
+    return v.value, g.value, t.value
 
 
-def mfhex_set_config(op: int, prec: int, nrhs: int, epb: int) -> None:
-    check(load().mfhex_set_config(op, prec, nrhs, epb), op)
+def mfhex_set_config(op: int, prec: int, nrhs: int, variant: int) -> None:
+    check(load().mfhex_set_config(op, prec, nrhs, variant), op)
 
 
 def mfhex_strerror(code: int) -> str:

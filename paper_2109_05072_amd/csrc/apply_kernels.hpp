@@ -1,32 +1,35 @@
 // Fused matrix-free operator kernels for gfx950, templated on the 1D sizes.
 //
-// One thread block holds `epb` elements; each element gets Q*Q threads.  The
-// element vector never leaves the chip: restriction (gather), the 1D basis
-// contractions along x, y, z, the pointwise geometric factors and the
-// transposed contractions run back to back in LDS and registers, and the
-// result is scatter-added into the output with hardware atomics.  This is
-// the operator-level fused form of Sec. 2 (w_L = A_L u_L with A^e = D^T G^e D,
-// the tensor derivatives D_r, D_s, D_t and six symmetric factors) with the
-// sum factorization of Sec. 1; the fusion of restriction, basis and
-// pointwise stages into one kernel follows the discussion of generated fused
-// operator kernels in Sec. 3.
+// One thread group (one wavefront, or two for the largest orders) owns G
+// elements and carries them through every stage of the operator without
+// leaving the chip: restriction (gather), the 1D basis contractions along x,
+// y and z, the pointwise geometric factors, the transposed contractions and
+// the scatter-add with hardware atomics.  This is the operator-level fused
+// form of Sec. 2 (w_L = A_L u_L with A^e = D^T G^e D: tensor derivatives
+// D_r, D_s, D_t and six symmetric factors per point), evaluated by the sum
+// factorization of Sec. 1; fusing restriction, basis and pointwise stages
+// into one kernel follows the generated fused operator kernels of Sec. 3.
 //
-// Contraction scheme ("pencils"): a 1D contraction along one axis is done by
-// threads that each own one full line (pencil) along that axis: the thread
-// reads the line from LDS into registers, multiplies by the small 1D matrix
-// (uniform across the block, so it sits in scalar registers / the scalar
-// cache), and writes the result line back in place.  LDS traffic is one read
-// per input and one write per output instead of one read per multiply-add.
-// The LDS array of an element is [c][b][a] with a fixed odd row pitch, so
-// lines along x (thread stride = pitch), y and z (thread stride 1) are
-// bank-conflict free, and every contraction can run in place.
+// Groups are independent: stages are separated by a wavefront-level sync
+// (no workgroup barrier) when a group is one wavefront, so memory latency in
+// one group is hidden by the others on the CU.
 //
-// Diffusion with Gauss points (q = p+2): values are interpolated to the
-// points along x, y, z (B), the reference gradient is taken with the
-// collocated derivative on the points (D, q x q), the 3x3 symmetric factors
-// are applied, and the transposes run in reverse order.  With Gauss-Lobatto
-// points collocated at the nodes (q = p+1) B is the identity and only D
-// remains.  Mass: interpolate, scale by w detJ, interpolate back.
+// Contractions ("pencils"): a 1D contraction along one axis is done by lanes
+// that each own whole lines (pencils) along that axis, R of them per lane:
+// the lane reads its lines from LDS into registers, then walks the output
+// index o in a rolled loop; row o of the small 1D matrix is uniform across
+// the group, so it is a short scalar load from a device copy of the matrix
+// and feeds R x NI fused multiply-adds from scalar registers.  LDS traffic is
+// one read per input and one write per output.  An element's LDS array is
+// [c][b][a] with an odd row pitch, so lines along x (lane stride = pitch), y
+// and z (lane stride 1) are conflict free, and contractions run in place.
+//
+// Diffusion with Gauss points (q = p+2): interpolate to the points along x,
+// y, z (B), take the reference gradient with the collocated derivative on the
+// points (D, q x q), apply the 3x3 symmetric factors, and run the transposes
+// in reverse order.  With Gauss-Lobatto points collocated at the nodes
+// (q = p+1) B is the identity.  Mass: interpolate, scale by w detJ,
+// interpolate back.
 #pragma once
 
 #include "mfhex_internal.h"
@@ -40,12 +43,12 @@ struct Lds {
     static constexpr int BUF = lds_buf(Q);
 };
 
-// 1D matrices passed by value as a kernel argument (constant, uniform).
-template <int P, int Q, typename T>
-struct BasisArg {
-    T B[Q * P];  // B[a*P + i]: node i -> point a
-    T D[Q * Q];  // D[a*Q + b]: derivative at point a of the point-b Lagrange polynomial
-};
+// Offsets of the matrices in the device basis block: B [Q][P], Bt [P][Q],
+// D [Q][Q], Dt [Q][Q], all row-major.
+constexpr int basis_b(int, int) { return 0; }
+constexpr int basis_bt(int P, int Q) { return Q * P; }
+constexpr int basis_d(int P, int Q) { return 2 * Q * P; }
+constexpr int basis_dt(int P, int Q) { return 2 * Q * P + Q * Q; }
 
 // Blocks are dealt to the 8 XCDs round-robin; renumber them so that each XCD
 // works on one contiguous range of elements (neighbouring elements share
@@ -57,344 +60,307 @@ __device__ __forceinline__ int64_t xcd_block(int64_t bid, int64_t nb)
     return x * q + (x < r ? x : r) + i;
 }
 
-// Contraction along x (axis 0) of lines (i1, i2), i1 < N1, i2 < N2:
-// dst[o] = sum_i M(o, i) src[i]; M(o,i) = M[o*LDM + i], or M[i*LDM + o] when TR.
-template <int NI, int NO, int N1, int N2, bool TR, int LDM, int Q, typename T>
-__device__ __forceinline__ void pencil_x(const T *src, T *dst, const T *__restrict__ M, int lt)
+// Stage separator.  A one-wavefront group needs no barrier: LDS operations
+// of a wavefront complete in order, so only compiler reordering is fenced.
+template <int NT>
+__device__ __forceinline__ void group_sync()
+{
+    if constexpr (NT <= 64) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        asm volatile("" ::: "memory");
+    } else {
+        __syncthreads();
+    }
+}
+
+// Contract axis AX of the G element arrays (extents E0 x E1 x E2 before the
+// contraction) from NI = E_AX to NO entries with M (row-major NO x NI):
+// dst[..o..] = sum_i M[o][i] src[..i..] (+ a1[..o..] + a2[..o..] with ADD2).
+// Every lane handles the same lines for a given (AX, extents), so a second
+// contraction along the same axis may follow without a sync.
+template <int AX, int E0, int E1, int E2, int NO, int G, int NT, int Q, typename T, bool ADD2 = false>
+__device__ __forceinline__ void contract(const T *src, T *dst, const T *__restrict__ M, int tid, const T *a1 = nullptr,
+                                         const T *a2 = nullptr)
 {
     using L = Lds<Q>;
-    if (lt < N1 * N2) {
-        const int i1 = lt % N1, i2 = lt / N1;
-        const int base = L::PITCH * i1 + L::PLANE * i2;
-        T v[NI];
+    constexpr int NI = AX == 0 ? E0 : AX == 1 ? E1 : E2;
+    constexpr int NA = AX == 0 ? E1 : E0;  // fastest-varying line index
+    constexpr int NB = AX == 2 ? E1 : E2;
+    constexpr int SA = AX == 0 ? L::PITCH : 1;
+    constexpr int SB = AX == 2 ? L::PITCH : L::PLANE;
+    constexpr int ST = AX == 0 ? 1 : AX == 1 ? L::PITCH : L::PLANE;  // stride along the line
+    constexpr int NPEN = G * NA * NB;
+    constexpr int R = (NPEN + NT - 1) / NT;
+    T v[R][NI];
+    int base[R];
 #pragma unroll
-        for (int i = 0; i < NI; ++i) v[i] = src[base + i];
+    for (int r = 0; r < R; ++r) {
+        const int id = tid + r * NT;
+        base[r] = -1;
+        if (id < NPEN) {
+            const int a = id % NA, t = id / NA, b = t % NB, g = t / NB;
+            base[r] = g * L::BUF + a * SA + b * SB;
 #pragma unroll
-        for (int o = 0; o < NO; ++o) {
-            T acc = T(0);
+            for (int i = 0; i < NI; ++i) v[r][i] = src[base[r] + i * ST];
+        }
+    }
+    // rows in flight per scalar-load wait: about 16 coefficients
+    constexpr int UR = NI >= 16 ? 1 : 16 / NI;
+#pragma unroll UR
+    for (int o = 0; o < NO; ++o) {
+        const T *row = M + o * NI;
 #pragma unroll
-            for (int i = 0; i < NI; ++i) acc += (TR ? M[i * LDM + o] : M[o * LDM + i]) * v[i];
-            dst[base + o] = acc;
+        for (int r = 0; r < R; ++r) {
+            if (base[r] >= 0) {
+                T acc = T(0);
+#pragma unroll
+                for (int i = 0; i < NI; ++i) acc += row[i] * v[r][i];
+                if constexpr (ADD2) acc += a1[base[r] + o * ST] + a2[base[r] + o * ST];
+                dst[base[r] + o * ST] = acc;
+            }
         }
     }
 }
 
-// Contraction along y (axis 1) of lines (i0, i2), i0 < N0, i2 < N2.
-template <int NI, int NO, int N0, int N2, bool TR, int LDM, int Q, typename T>
-__device__ __forceinline__ void pencil_y(const T *src, T *dst, const T *__restrict__ M, int lt)
+// Restriction: element values into s0 of each of the G elements.  All loads
+// are issued before any is used (masked nodes read node 0 and are zeroed).
+template <int P, int Q, int G, int NT, int NOFF, typename T>
+__device__ __forceinline__ void gather(T *s0, const int32_t (&off)[NOFF], const T *__restrict__ x, int nvec, int v,
+                                       int tid)
 {
     using L = Lds<Q>;
-    if (lt < N0 * N2) {
-        const int i0 = lt % N0, i2 = lt / N0;
-        const int base = i0 + L::PLANE * i2;
-        T v[NI];
+    constexpr int P3 = P * P * P;
+    T val[NOFF];
 #pragma unroll
-        for (int i = 0; i < NI; ++i) v[i] = src[base + L::PITCH * i];
-#pragma unroll
-        for (int o = 0; o < NO; ++o) {
-            T acc = T(0);
-#pragma unroll
-            for (int i = 0; i < NI; ++i) acc += (TR ? M[i * LDM + o] : M[o * LDM + i]) * v[i];
-            dst[base + L::PITCH * o] = acc;
-        }
-    }
-}
-
-// Restriction: element values into s0[k][j][i] (zero at masked nodes).
-template <int P, int Q, int NOFF, typename T>
-__device__ __forceinline__ void gather(T *s0, const int32_t (&off)[NOFF], const T *__restrict__ x, int nvec,
-                                       int v, int lt)
-{
-    using L = Lds<Q>;
-    constexpr int Q2 = Q * Q, P3 = P * P * P;
+    for (int r = 0; r < NOFF; ++r) val[r] = x[(int64_t)(off[r] >= 0 ? off[r] : 0) * nvec + v];
 #pragma unroll
     for (int r = 0; r < NOFF; ++r) {
-        const int t = lt + r * Q2;
-        if (t < P3) {
+        const int id = tid + r * NT;
+        if (id < G * P3) {
+            const int g = id / P3, t = id - g * P3;
             const int i = t % P, j = (t / P) % P, k = t / (P * P);
-            const int32_t o = off[r];
-            s0[i + L::PITCH * j + L::PLANE * k] = o >= 0 ? x[(int64_t)o * nvec + v] : T(0);
+            s0[g * L::BUF + i + L::PITCH * j + L::PLANE * k] = off[r] >= 0 ? val[r] : T(0);
         }
     }
 }
 
-// Transposed restriction: y[node] += s0[k][j][i] for unmasked nodes.
-template <int P, int Q, int NOFF, typename T>
+// Transposed restriction: y[node] += s0 for unmasked nodes.
+template <int P, int Q, int G, int NT, int NOFF, typename T>
 __device__ __forceinline__ void scatter_add(const T *s0, const int32_t (&off)[NOFF], T *__restrict__ y, int nvec,
-                                            int v, int lt)
+                                            int v, int tid)
 {
     using L = Lds<Q>;
-    constexpr int Q2 = Q * Q, P3 = P * P * P;
+    constexpr int P3 = P * P * P;
 #pragma unroll
     for (int r = 0; r < NOFF; ++r) {
-        const int t = lt + r * Q2;
-        if (t < P3 && off[r] >= 0) {
+        const int id = tid + r * NT;
+        if (id < G * P3 && off[r] >= 0) {
+            const int g = id / P3, t = id - g * P3;
             const int i = t % P, j = (t / P) % P, k = t / (P * P);
-            unsafeAtomicAdd(&y[(int64_t)off[r] * nvec + v], s0[i + L::PITCH * j + L::PLANE * k]);
+            unsafeAtomicAdd(&y[(int64_t)off[r] * nvec + v], s0[g * L::BUF + i + L::PITCH * j + L::PLANE * k]);
         }
     }
 }
 
-// Gathered element in s0 -> values at the points of column (a, b) in col[].
-// For Gauss points the x and y interpolations run as pencils through LDS and
-// the z interpolation in registers.  Ends without a trailing barrier.
-template <int P, int Q, bool COLLOC, typename T>
-__device__ __forceinline__ void interp_to_column(T *s0, const BasisArg<P, Q, T> &bas, int lt, int a, int b,
-                                                 T (&col)[Q])
+// Nodes (s0) -> values at the points (s0).  Ends with a sync.
+template <int P, int Q, bool COLLOC, int G, int NT, typename T>
+__device__ __forceinline__ void interp(T *s0, const T *__restrict__ bas, int tid)
 {
-    using L = Lds<Q>;
     if constexpr (!COLLOC) {
-        pencil_x<P, Q, P, P, false, P, Q>(s0, s0, bas.B, lt);
-        __syncthreads();
-        pencil_y<P, Q, Q, P, false, P, Q>(s0, s0, bas.B, lt);
-        __syncthreads();
-        T in[P];
-#pragma unroll
-        for (int k = 0; k < P; ++k) in[k] = s0[a + L::PITCH * b + L::PLANE * k];
-#pragma unroll
-        for (int c = 0; c < Q; ++c) {
-            T acc = T(0);
-#pragma unroll
-            for (int k = 0; k < P; ++k) acc += bas.B[c * P + k] * in[k];
-            col[c] = acc;
-        }
-    } else {
-#pragma unroll
-        for (int c = 0; c < Q; ++c) col[c] = s0[a + L::PITCH * b + L::PLANE * c];
+        contract<0, P, P, P, Q, G, NT, Q>(s0, s0, bas + basis_b(P, Q), tid);
+        group_sync<NT>();
+        contract<1, Q, P, P, Q, G, NT, Q>(s0, s0, bas + basis_b(P, Q), tid);
+        group_sync<NT>();
+        contract<2, Q, Q, P, Q, G, NT, Q>(s0, s0, bas + basis_b(P, Q), tid);
+        group_sync<NT>();
     }
 }
 
-// Column (a, b) of point values -> transposed interpolation back to the
-// element's nodes, left in s0[k][j][i].  Ends with a barrier.
-template <int P, int Q, bool COLLOC, typename T>
-__device__ __forceinline__ void column_to_nodes(T *s0, const BasisArg<P, Q, T> &bas, int lt, int a, int b,
-                                                const T (&col)[Q])
+// Values at the points in s0 -> reference gradient: d/dr in s1, d/ds in s2,
+// d/dt in s0.  Ends with a sync.
+template <int P, int Q, int G, int NT, typename T>
+__device__ __forceinline__ void grad(T *s0, T *s1, T *s2, const T *__restrict__ bas, int tid)
 {
-    using L = Lds<Q>;
-    if constexpr (!COLLOC) {
-#pragma unroll
-        for (int k = 0; k < P; ++k) {
-            T acc = T(0);
-#pragma unroll
-            for (int c = 0; c < Q; ++c) acc += bas.B[c * P + k] * col[c];
-            s0[a + L::PITCH * b + L::PLANE * k] = acc;
-        }
-        __syncthreads();
-        pencil_y<Q, P, Q, P, true, P, Q>(s0, s0, bas.B, lt);
-        __syncthreads();
-        pencil_x<Q, P, P, P, true, P, Q>(s0, s0, bas.B, lt);
-        __syncthreads();
-    } else {
-#pragma unroll
-        for (int c = 0; c < Q; ++c) s0[a + L::PITCH * b + L::PLANE * c] = col[c];
-        __syncthreads();
-    }
-}
-
-// Gathered element in s0 -> reference gradient at every point: d/dr in s1,
-// d/ds in s2 (both [c][b][a]), d/dt of column (a, b) in dz[].  Ends with a
-// barrier.  s0 then holds the point values.
-template <int P, int Q, bool COLLOC, typename T>
-__device__ __forceinline__ void gradient(T *s0, T *s1, T *s2, const BasisArg<P, Q, T> &bas, int lt, int a, int b,
-                                         T (&dz)[Q])
-{
-    using L = Lds<Q>;
-    T col[Q];
-    interp_to_column<P, Q, COLLOC, T>(s0, bas, lt, a, b, col);
-#pragma unroll
-    for (int c = 0; c < Q; ++c) {
-        T acc = T(0);
-#pragma unroll
-        for (int d = 0; d < Q; ++d) acc += bas.D[c * Q + d] * col[d];
-        dz[c] = acc;
-    }
-    if constexpr (!COLLOC) {
-#pragma unroll
-        for (int c = 0; c < Q; ++c) s0[a + L::PITCH * b + L::PLANE * c] = col[c];
-        __syncthreads();
-    }
-    pencil_x<Q, Q, Q, Q, false, Q, Q>(s0, s1, bas.D, lt);
-    pencil_y<Q, Q, Q, Q, false, Q, Q>(s0, s2, bas.D, lt);
-    __syncthreads();
+    contract<0, Q, Q, Q, Q, G, NT, Q>(s0, s1, bas + basis_d(P, Q), tid);
+    contract<1, Q, Q, Q, Q, G, NT, Q>(s0, s2, bas + basis_d(P, Q), tid);
+    group_sync<NT>();
+    contract<2, Q, Q, Q, Q, G, NT, Q>(s0, s0, bas + basis_d(P, Q), tid);
+    group_sync<NT>();
 }
 
 // ---------------------------------------------------------------------------
 // y += A x  (mass / diffusion), or y += B^T (w detJ f) for the load vector.
 // ---------------------------------------------------------------------------
-template <int P, int Q, bool COLLOC, int MODE, bool VARK, typename T>
-__global__ void __launch_bounds__(kMaxThreads)
-k_apply(const BasisArg<P, Q, T> bas, const int64_t nelem, const int nvec, const int32_t *__restrict__ offsets,
+template <int P, int Q, bool COLLOC, int MODE, bool VARK, typename T, int G, int NT>
+__global__ void __launch_bounds__(NT)
+k_apply(const T *__restrict__ bas, const int64_t nelem, const int nvec, const int32_t *__restrict__ offsets,
         const T *__restrict__ qdata, const double *__restrict__ kappa, const double *__restrict__ wdet,
         const T *__restrict__ x, T *__restrict__ y)
 {
     constexpr int Q2 = Q * Q, Q3 = Q2 * Q, P3 = P * P * P;
-    constexpr int NOFF = (P3 + Q2 - 1) / Q2;
-    constexpr int NBUF = apply_nbuf(MODE);
+    constexpr int NOFF = (G * P3 + NT - 1) / NT;
+    constexpr int NPT = G * Q3, RQ = (NPT + NT - 1) / NT;
     using L = Lds<Q>;
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    T *const sm = reinterpret_cast<T *>(smem_raw);
-    const int epb = blockDim.x / Q2;
-    const int el = threadIdx.x / Q2, lt = threadIdx.x - el * Q2;
-    T *const s0 = sm + (size_t)el * NBUF * L::BUF;
-    T *const s1 = s0 + L::BUF;
-    T *const s2 = s1 + L::BUF;
-    const int64_t e = xcd_block(blockIdx.x, gridDim.x) * epb + el;
-    const bool valid = e < nelem;
-    const int a = lt % Q, b = lt / Q;
+    T *const s0 = reinterpret_cast<T *>(smem_raw);
+    T *const s1 = s0 + G * L::BUF;
+    T *const s2 = s1 + G * L::BUF;
+    const int tid = threadIdx.x;
+    const int64_t e0 = xcd_block(blockIdx.x, gridDim.x) * G;
 
     int32_t off[NOFF];
 #pragma unroll
     for (int r = 0; r < NOFF; ++r) {
-        const int t = lt + r * Q2;
-        off[r] = (valid && t < P3) ? offsets[e * P3 + t] : -1;
+        const int id = tid + r * NT;
+        const int g = id / P3;
+        off[r] = (id < G * P3 && e0 + g < nelem) ? offsets[e0 * P3 + id] : -1;
     }
 
     for (int v = 0; v < nvec; ++v) {
-        T col[Q];
         if constexpr (MODE == kRhs) {
             const double *f = reinterpret_cast<const double *>(x);
-#pragma unroll
-            for (int c = 0; c < Q; ++c) {
-                const int64_t pt = e * Q3 + a + Q * b + Q2 * c;
-                col[c] = valid ? T(wdet[pt] * f[pt]) : T(0);
-            }
-        } else if constexpr (MODE == kMass) {
-            gather<P, Q, NOFF, T>(s0, off, x, nvec, v, lt);
-            __syncthreads();
-            interp_to_column<P, Q, COLLOC, T>(s0, bas, lt, a, b, col);
-            const T *qd = qdata + e * Q3;
-#pragma unroll
-            for (int c = 0; c < Q; ++c) {
-                const int pt = a + Q * b + Q2 * c;
-                const T w = valid ? __builtin_nontemporal_load(&qd[pt]) : T(0);
-                col[c] *= w;
-            }
-        } else {  // diffusion
-            gather<P, Q, NOFF, T>(s0, off, x, nvec, v, lt);
-            __syncthreads();
-            T dz[Q];
-            gradient<P, Q, COLLOC, T>(s0, s1, s2, bas, lt, a, b, dz);
-            // The point values in s0 are no longer needed: park d/dt there so
-            // the pointwise loop below carries no register arrays.
-#pragma unroll
-            for (int c = 0; c < Q; ++c) s0[a + L::PITCH * b + L::PLANE * c] = dz[c];
-            const T *qd = qdata + e * (kQdDiff * Q3);
-#pragma unroll 2
-            for (int c = 0; c < Q; ++c) {
-                const int pt = a + Q * b + Q2 * c;
-                const int ls = a + L::PITCH * b + L::PLANE * c;
-                T g[kQdDiff];
-#pragma unroll
-                for (int m = 0; m < kQdDiff; ++m) g[m] = valid ? __builtin_nontemporal_load(&qd[m * Q3 + pt]) : T(0);
-                if constexpr (VARK) {
-                    const T kap = valid ? T(kappa[e * Q3 + pt]) : T(0);
-#pragma unroll
-                    for (int m = 0; m < kQdDiff; ++m) g[m] *= kap;
+#pragma unroll 4
+            for (int k = 0; k < RQ; ++k) {
+                const int id = tid + k * NT;
+                if (id < NPT) {
+                    const int g = id / Q3, pt = id - g * Q3;
+                    const int a = pt % Q, b = (pt / Q) % Q, c = pt / Q2;
+                    const int64_t gp = (e0 + g < nelem ? e0 + g : nelem - 1) * Q3 + pt;
+                    s0[g * L::BUF + a + L::PITCH * b + L::PLANE * c] = T(wdet[gp] * f[gp]);
                 }
-                const T ur = s1[ls], us = s2[ls], ut = s0[ls];
-                s1[ls] = g[0] * ur + g[5] * us + g[4] * ut;
-                s2[ls] = g[5] * ur + g[1] * us + g[3] * ut;
-                s0[ls] = g[4] * ur + g[3] * us + g[2] * ut;
             }
-            // transposed t-derivative of the own column (no barrier needed)
+            group_sync<NT>();
+        } else {
+            gather<P, Q, G, NT, NOFF, T>(s0, off, x, nvec, v, tid);
+            group_sync<NT>();
+            interp<P, Q, COLLOC, G, NT, T>(s0, bas, tid);
+            if constexpr (MODE == kMass) {
+#pragma unroll 4
+                for (int k = 0; k < RQ; ++k) {
+                    const int id = tid + k * NT;
+                    if (id < NPT) {
+                        const int g = id / Q3, pt = id - g * Q3;
+                        const int a = pt % Q, b = (pt / Q) % Q, c = pt / Q2;
+                        const int ls = g * L::BUF + a + L::PITCH * b + L::PLANE * c;
+                        const int64_t e = e0 + g < nelem ? e0 + g : nelem - 1;
+                        s0[ls] *= __builtin_nontemporal_load(&qdata[e * Q3 + pt]);
+                    }
+                }
+                group_sync<NT>();
+            } else {
+                grad<P, Q, G, NT, T>(s0, s1, s2, bas, tid);
+#pragma unroll 4
+                for (int k = 0; k < RQ; ++k) {
+                    const int id = tid + k * NT;
+                    if (id < NPT) {
+                        const int g = id / Q3, pt = id - g * Q3;
+                        const int a = pt % Q, b = (pt / Q) % Q, c = pt / Q2;
+                        const int ls = g * L::BUF + a + L::PITCH * b + L::PLANE * c;
+                        // the tail group reads the last element's data (and scatters nothing)
+                        const int64_t e = e0 + g < nelem ? e0 + g : nelem - 1;
+                        const T *qd = qdata + e * (kQdDiff * Q3) + pt;
+                        T gm[kQdDiff];
 #pragma unroll
-            for (int c = 0; c < Q; ++c) dz[c] = s0[a + L::PITCH * b + L::PLANE * c];
+                        for (int m = 0; m < kQdDiff; ++m) gm[m] = __builtin_nontemporal_load(&qd[m * Q3]);
+                        if constexpr (VARK) {
+                            const T kap = T(kappa[e * Q3 + pt]);
 #pragma unroll
-            for (int c = 0; c < Q; ++c) {
-                T acc = T(0);
-#pragma unroll
-                for (int d = 0; d < Q; ++d) acc += bas.D[d * Q + c] * dz[d];
-                col[c] = acc;
-            }
-            __syncthreads();
-            pencil_x<Q, Q, Q, Q, true, Q, Q>(s1, s1, bas.D, lt);
-            pencil_y<Q, Q, Q, Q, true, Q, Q>(s2, s2, bas.D, lt);
-            __syncthreads();
-#pragma unroll
-            for (int c = 0; c < Q; ++c) {
-                const int ls = a + L::PITCH * b + L::PLANE * c;
-                col[c] += s1[ls] + s2[ls];
+                            for (int m = 0; m < kQdDiff; ++m) gm[m] *= kap;
+                        }
+                        const T ur = s1[ls], us = s2[ls], ut = s0[ls];
+                        s1[ls] = gm[0] * ur + gm[5] * us + gm[4] * ut;
+                        s2[ls] = gm[5] * ur + gm[1] * us + gm[3] * ut;
+                        s0[ls] = gm[4] * ur + gm[3] * us + gm[2] * ut;
+                    }
+                }
+                group_sync<NT>();
+                // transposed gradient: x and y lines in place, then the z lines
+                // of s0 with the x and y parts added
+                contract<0, Q, Q, Q, Q, G, NT, Q>(s1, s1, bas + basis_dt(P, Q), tid);
+                contract<1, Q, Q, Q, Q, G, NT, Q>(s2, s2, bas + basis_dt(P, Q), tid);
+                group_sync<NT>();
+                contract<2, Q, Q, Q, Q, G, NT, Q, T, true>(s0, s0, bas + basis_dt(P, Q), tid, s1, s2);
+                // same lines, same lanes: B^T along z follows without a sync
             }
         }
-        column_to_nodes<P, Q, COLLOC, T>(s0, bas, lt, a, b, col);
-        if (valid) scatter_add<P, Q, NOFF, T>(s0, off, y, nvec, v, lt);
-        __syncthreads();
+        // transposed interpolation back to the nodes
+        if constexpr (!COLLOC) {
+            contract<2, Q, Q, Q, P, G, NT, Q>(s0, s0, bas + basis_bt(P, Q), tid);
+            group_sync<NT>();
+            contract<1, Q, Q, P, P, G, NT, Q>(s0, s0, bas + basis_bt(P, Q), tid);
+            group_sync<NT>();
+            contract<0, Q, P, P, P, G, NT, Q>(s0, s0, bas + basis_bt(P, Q), tid);
+        }
+        group_sync<NT>();
+        scatter_add<P, Q, G, NT, NOFF, T>(s0, off, y, nvec, v, tid);
+        group_sync<NT>();
     }
 }
 
 // ---------------------------------------------------------------------------
 // Coefficient gradient g[e][pt] = (Dhat r)^T G0 (Dhat u) at every point.
 // ---------------------------------------------------------------------------
-template <int P, int Q, bool COLLOC>
-__global__ void __launch_bounds__(kMaxThreads)
-k_kgrad(const BasisArg<P, Q, double> bas, const int64_t nelem, const int32_t *__restrict__ offsets,
+template <int P, int Q, bool COLLOC, int G, int NT>
+__global__ void __launch_bounds__(NT)
+k_kgrad(const double *__restrict__ bas, const int64_t nelem, const int32_t *__restrict__ offsets,
         const double *__restrict__ qdata, const double *__restrict__ u, const double *__restrict__ r,
-        double *__restrict__ g)
+        double *__restrict__ gout)
 {
     using T = double;
     constexpr int Q2 = Q * Q, Q3 = Q2 * Q, P3 = P * P * P;
-    constexpr int NOFF = (P3 + Q2 - 1) / Q2;
+    constexpr int NOFF = (G * P3 + NT - 1) / NT;
+    constexpr int NPT = G * Q3, RQ = (NPT + NT - 1) / NT;
     using L = Lds<Q>;
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    T *const sm = reinterpret_cast<T *>(smem_raw);
-    const int epb = blockDim.x / Q2;
-    const int el = threadIdx.x / Q2, lt = threadIdx.x - el * Q2;
-    T *const s0 = sm + (size_t)el * 3 * L::BUF;
-    T *const s1 = s0 + L::BUF;
-    T *const s2 = s1 + L::BUF;
-    const int64_t e = xcd_block(blockIdx.x, gridDim.x) * epb + el;
-    const bool valid = e < nelem;
-    const int a = lt % Q, b = lt / Q;
-
+    T *const s0 = reinterpret_cast<T *>(smem_raw);
+    T *const s1 = s0 + G * L::BUF;
+    T *const s2 = s1 + G * L::BUF;
+    T *const t0 = s2 + G * L::BUF;
+    T *const t1 = t0 + G * L::BUF;
+    T *const t2 = t1 + G * L::BUF;
+    const int tid = threadIdx.x;
+    const int64_t e0 = xcd_block(blockIdx.x, gridDim.x) * G;
     int32_t off[NOFF];
 #pragma unroll
     for (int rr = 0; rr < NOFF; ++rr) {
-        const int t = lt + rr * Q2;
-        off[rr] = (valid && t < P3) ? offsets[e * P3 + t] : -1;
+        const int id = tid + rr * NT;
+        const int g = id / P3;
+        off[rr] = (id < G * P3 && e0 + g < nelem) ? offsets[e0 * P3 + id] : -1;
     }
-    T ur[Q], us[Q], ut[Q];
-    gather<P, Q, NOFF, T>(s0, off, u, 1, 0, lt);
-    __syncthreads();
-    gradient<P, Q, COLLOC, T>(s0, s1, s2, bas, lt, a, b, ut);
+    gather<P, Q, G, NT, NOFF, T>(s0, off, u, 1, 0, tid);
+    gather<P, Q, G, NT, NOFF, T>(t0, off, r, 1, 0, tid);
+    group_sync<NT>();
+    interp<P, Q, COLLOC, G, NT, T>(s0, bas, tid);
+    interp<P, Q, COLLOC, G, NT, T>(t0, bas, tid);
+    grad<P, Q, G, NT, T>(s0, s1, s2, bas, tid);
+    grad<P, Q, G, NT, T>(t0, t1, t2, bas, tid);
+#pragma unroll 4
+    for (int k = 0; k < RQ; ++k) {
+        const int id = tid + k * NT;
+        if (id < NPT) {
+            const int g = id / Q3, pt = id - g * Q3;
+            if (e0 + g < nelem) {
+                const int a = pt % Q, b = (pt / Q) % Q, c = pt / Q2;
+                const int ls = g * L::BUF + a + L::PITCH * b + L::PLANE * c;
+                const T *qd = qdata + (e0 + g) * (kQdDiff * Q3) + pt;
+                T gm[kQdDiff];
 #pragma unroll
-    for (int c = 0; c < Q; ++c) {
-        const int ls = a + L::PITCH * b + L::PLANE * c;
-        ur[c] = s1[ls];
-        us[c] = s2[ls];
-    }
-    __syncthreads();
-    T rt[Q];
-    gather<P, Q, NOFF, T>(s0, off, r, 1, 0, lt);
-    __syncthreads();
-    gradient<P, Q, COLLOC, T>(s0, s1, s2, bas, lt, a, b, rt);
-    if (!valid) return;  // no barrier follows
-    const T *qd = qdata + e * (kQdDiff * Q3);
-#pragma unroll
-    for (int c = 0; c < Q; ++c) {
-        const int pt = a + Q * b + Q2 * c;
-        const int ls = a + L::PITCH * b + L::PLANE * c;
-        T gm[kQdDiff];
-#pragma unroll
-        for (int m = 0; m < kQdDiff; ++m) gm[m] = __builtin_nontemporal_load(&qd[m * Q3 + pt]);
-        const T vr = gm[0] * ur[c] + gm[5] * us[c] + gm[4] * ut[c];
-        const T vs = gm[5] * ur[c] + gm[1] * us[c] + gm[3] * ut[c];
-        const T vt = gm[4] * ur[c] + gm[3] * us[c] + gm[2] * ut[c];
-        __builtin_nontemporal_store(s1[ls] * vr + s2[ls] * vs + rt[c] * vt, &g[e * Q3 + pt]);
+                for (int m = 0; m < kQdDiff; ++m) gm[m] = __builtin_nontemporal_load(&qd[m * Q3]);
+                const T ur = s1[ls], us = s2[ls], ut = s0[ls];
+                const T vr = gm[0] * ur + gm[5] * us + gm[4] * ut;
+                const T vs = gm[5] * ur + gm[1] * us + gm[3] * ut;
+                const T vt = gm[4] * ur + gm[3] * us + gm[2] * ut;
+                __builtin_nontemporal_store(t1[ls] * vr + t2[ls] * vs + t0[ls] * vt, &gout[(e0 + g) * Q3 + pt]);
+            }
+        }
     }
 }
 
 // ---------------------------------------------------------------------------
 // Host launchers for one (P, Q) pair.
 // ---------------------------------------------------------------------------
-template <int P, int Q, typename T>
-static BasisArg<P, Q, T> make_basis_arg(const Basis1D &b)
-{
-    BasisArg<P, Q, T> o;
-    for (int i = 0; i < Q * P; ++i) o.B[i] = T(b.B[i]);
-    for (int i = 0; i < Q * Q; ++i) o.D[i] = T(b.D[i]);
-    return o;
-}
-
 template <typename K>
 static hipError_t prepare_lds(K kernel, size_t lds)
 {
@@ -403,19 +369,29 @@ static hipError_t prepare_lds(K kernel, size_t lds)
     return hipSuccess;
 }
 
+template <int P, int Q, bool COLLOC, int MODE, bool VARK, typename T, int G, int NT>
+static hipError_t launch_apply_v(const ApplyLaunch &a)
+{
+    const int64_t nblk = (a.v.nelem + G - 1) / G;
+    const size_t lds = (size_t)G * apply_nbuf(MODE) * Lds<Q>::BUF * sizeof(T);
+    auto kern = k_apply<P, Q, COLLOC, MODE, VARK, T, G, NT>;
+    hipError_t err = prepare_lds(kern, lds);
+    if (err != hipSuccess) return err;
+    hipLaunchKernelGGL(kern, dim3((unsigned)nblk), dim3(NT), lds, a.stream, static_cast<const T *>(a.basis_dev),
+                       a.v.nelem, a.nvec, a.v.offsets, static_cast<const T *>(a.v.qdata), a.v.kappa, a.wdet,
+                       static_cast<const T *>(a.x), static_cast<T *>(a.y));
+    return hipGetLastError();
+}
+
 template <int P, int Q, bool COLLOC, int MODE, bool VARK, typename T>
 static hipError_t launch_apply_t(const ApplyLaunch &a)
 {
-    const auto bas = make_basis_arg<P, Q, T>(*a.basis);
-    const int64_t nblk = (a.v.nelem + a.epb - 1) / a.epb;
-    const size_t lds = (size_t)a.epb * apply_nbuf(MODE) * Lds<Q>::BUF * sizeof(T);
-    auto kern = k_apply<P, Q, COLLOC, MODE, VARK, T>;
-    hipError_t err = prepare_lds(kern, lds);
-    if (err != hipSuccess) return err;
-    hipLaunchKernelGGL(kern, dim3((unsigned)nblk), dim3(a.epb * Q * Q), lds, a.stream, bas, a.v.nelem, a.nvec,
-                       a.v.offsets, static_cast<const T *>(a.v.qdata), a.v.kappa, a.wdet,
-                       static_cast<const T *>(a.x), static_cast<T *>(a.y));
-    return hipGetLastError();
+    switch (a.variant) {
+    case 0: return launch_apply_v<P, Q, COLLOC, MODE, VARK, T, variant_g(Q, 0), variant_nt(Q, 0)>(a);
+    case 1: return launch_apply_v<P, Q, COLLOC, MODE, VARK, T, variant_g(Q, 1), variant_nt(Q, 1)>(a);
+    case 2: return launch_apply_v<P, Q, COLLOC, MODE, VARK, T, variant_g(Q, 2), variant_nt(Q, 2)>(a);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 template <int P, int Q, bool COLLOC>
@@ -434,14 +410,14 @@ static hipError_t launch_apply_pq(const ApplyLaunch &a)
 template <int P, int Q, bool COLLOC>
 static hipError_t launch_kgrad_pq(const KgradLaunch &a)
 {
-    const auto bas = make_basis_arg<P, Q, double>(*a.basis);
-    const int64_t nblk = (a.v.nelem + a.epb - 1) / a.epb;
-    const size_t lds = (size_t)a.epb * 3 * Lds<Q>::BUF * sizeof(double);
-    auto kern = k_kgrad<P, Q, COLLOC>;
+    constexpr int G = 1, NT = Q <= 6 ? 64 : 128;
+    const int64_t nblk = a.v.nelem;
+    const size_t lds = (size_t)G * 6 * Lds<Q>::BUF * sizeof(double);
+    auto kern = k_kgrad<P, Q, COLLOC, G, NT>;
     hipError_t err = prepare_lds(kern, lds);
     if (err != hipSuccess) return err;
-    hipLaunchKernelGGL(kern, dim3((unsigned)nblk), dim3(a.epb * Q * Q), lds, a.stream, bas, a.v.nelem,
-                       a.v.offsets, static_cast<const double *>(a.v.qdata), a.u, a.r, a.g);
+    hipLaunchKernelGGL(kern, dim3((unsigned)nblk), dim3(NT), lds, a.stream, a.basis_dev, a.v.nelem, a.v.offsets,
+                       static_cast<const double *>(a.v.qdata), a.u, a.r, a.g);
     return hipGetLastError();
 }
 
@@ -452,12 +428,12 @@ static hipError_t launch_kgrad_pq(const KgradLaunch &a)
     namespace mfhex {                                                                                  \
     hipError_t launch_apply_p##N(const ApplyLaunch &a)                                                 \
     {                                                                                                  \
-        if (a.basis->colloc) return launch_apply_pq<N + 1, N + 1, true>(a);                            \
+        if (a.colloc) return launch_apply_pq<N + 1, N + 1, true>(a);                                   \
         return launch_apply_pq<N + 1, N + 2, false>(a);                                                \
     }                                                                                                  \
     hipError_t launch_kgrad_p##N(const KgradLaunch &a)                                                 \
     {                                                                                                  \
-        if (a.basis->colloc) return launch_kgrad_pq<N + 1, N + 1, true>(a);                            \
+        if (a.colloc) return launch_kgrad_pq<N + 1, N + 1, true>(a);                                   \
         return launch_kgrad_pq<N + 1, N + 2, false>(a);                                                \
     }                                                                                                  \
     }

@@ -7,6 +7,7 @@
 #include <cstdint>
 #include <cstring>
 #include <string>
+#include <vector>
 
 #include "blas.h"
 #include "op.h"
@@ -78,6 +79,8 @@ Layout workspace_layout(const mfhex_desc &d, int64_t E, int P, int Q)
         L.wdet = o;
         o += al(E * Q3 * sizeof(double));
     }
+    L.basis = o;
+    o += al(basis_len(P, Q) * (sizeof(double) + sizeof(float)) + 256);
     L.bad = o;
     o += 256;
     L.total = o;
@@ -125,36 +128,30 @@ int check_hip(mfhex_op op, hipError_t e, const char *what)
 
 int mode_of(const mfhex_op_s &op) { return op.d.kind == MFHEX_DIFFUSION ? kDiff : kMass; }
 
-static size_t lds_bytes(const mfhex_op_s &op, int prec, int epb)
+bool valid_variant(const mfhex_op_s &op, int prec, int variant)
 {
-    const size_t s = prec == MFHEX_F32 ? 4 : 8;
-    return (size_t)epb * apply_nbuf(mode_of(op)) * lds_buf(op.Q) * s;
+    (void)op;
+    return (prec == MFHEX_F64 || prec == MFHEX_F32) && variant >= 0 && variant < kNumVariants;
 }
 
-bool valid_epb(const mfhex_op_s &op, int prec, int epb)
+int default_variant(const mfhex_op_s &op, int prec, int nvec)
 {
-    return epb >= 1 && epb * op.Q * op.Q <= kMaxThreads && lds_bytes(op, prec, epb) <= 65536;
-}
-
-int default_epb(const mfhex_op_s &op, int prec, int nvec)
-{
+    (void)op;
+    (void)prec;
     (void)nvec;
-    int e = 256 / (op.Q * op.Q);
-    if (e < 1) e = 1;
-    while (e > 1 && !valid_epb(op, prec, e)) --e;
-    return e;
+    return 0;
 }
 
-int epb_for(const mfhex_op_s &op, int prec, int nvec)
+int variant_for(const mfhex_op_s &op, int prec, int nvec)
 {
-    auto it = op.epb.find({prec, nvec});
-    if (it != op.epb.end()) return it->second;
-    return default_epb(op, prec, nvec);
+    auto it = op.variant.find({prec, nvec});
+    if (it != op.variant.end()) return it->second;
+    return default_variant(op, prec, nvec);
 }
 
 hipError_t launch_apply(const ApplyLaunch &a)
 {
-    switch (a.basis->P - 1) {
+    switch (a.P - 1) {
     case 1: return launch_apply_p1(a);
     case 2: return launch_apply_p2(a);
     case 3: return launch_apply_p3(a);
@@ -169,7 +166,7 @@ hipError_t launch_apply(const ApplyLaunch &a)
 
 hipError_t launch_kgrad(const KgradLaunch &a)
 {
-    switch (a.basis->P - 1) {
+    switch (a.P - 1) {
     case 1: return launch_kgrad_p1(a);
     case 2: return launch_kgrad_p2(a);
     case 3: return launch_kgrad_p3(a);
@@ -198,7 +195,7 @@ static OpView view_of(const mfhex_op_s &op, int prec)
     return v;
 }
 
-int apply_impl(mfhex_op op, int prec, int nrhs, const void *x, void *y, hipStream_t s, bool zero, int epb_override)
+int apply_impl(mfhex_op op, int prec, int nrhs, const void *x, void *y, hipStream_t s, bool zero, int variant)
 {
     if (!op) return set_error(nullptr, MFHEX_ERR_ARG, "null handle");
     if (prec != MFHEX_F64 && prec != MFHEX_F32) return set_error(op, MFHEX_ERR_ARG, "prec must be F64 or F32");
@@ -213,20 +210,22 @@ int apply_impl(mfhex_op op, int prec, int nrhs, const void *x, void *y, hipStrea
     const size_t bytes = (size_t)op->N * nvec * (prec == MFHEX_F32 ? 4 : 8);
     const uintptr_t xa = (uintptr_t)x, ya = (uintptr_t)y;
     if (xa < ya + bytes && ya < xa + bytes) return set_error(op, MFHEX_ERR_ARG, "x and y overlap");
-    const int epb = epb_override > 0 ? epb_override : epb_for(*op, prec, nvec);
-    if (!valid_epb(*op, prec, epb)) return set_error(op, MFHEX_ERR_ARG, "invalid elements-per-block");
+    const int var = variant >= 0 ? variant : variant_for(*op, prec, nvec);
+    if (!valid_variant(*op, prec, var)) return set_error(op, MFHEX_ERR_ARG, "invalid launch variant");
     if (zero) {
         const int c = check_hip(op, hipMemsetAsync(y, 0, bytes, s), "hipMemsetAsync");
         if (c) return c;
     }
     ApplyLaunch a{};
     a.v = view_of(*op, prec);
-    a.basis = &op->basis;
+    a.P = op->P;
+    a.colloc = op->basis.colloc;
+    a.basis_dev = prec == MFHEX_F32 ? (const void *)op->basis32 : (const void *)op->basis64;
     a.prec = prec;
     a.mode = mode_of(*op);
     a.vark = op->d.variable_kappa;
     a.nvec = nvec;
-    a.epb = epb;
+    a.variant = var;
     a.x = x;
     a.y = y;
     a.wdet = nullptr;
@@ -286,6 +285,8 @@ int mfhex_create(const mfhex_desc *d, void *workspace_dev, size_t workspace_byte
     op->kappa = L.kappa == SIZE_MAX ? nullptr : reinterpret_cast<double *>(ws + L.kappa);
     op->wdet = L.wdet == SIZE_MAX ? nullptr : reinterpret_cast<double *>(ws + L.wdet);
     op->bad = reinterpret_cast<int32_t *>(ws + L.bad);
+    op->basis64 = reinterpret_cast<double *>(ws + L.basis);
+    op->basis32 = reinterpret_cast<float *>(ws + L.basis + ((basis_len(op->P, op->Q) * sizeof(double) + 255) & ~size_t(255)));
     hipStream_t s = static_cast<hipStream_t>(stream);
     auto bail = [&](int code) {
         g_err = op->err;
@@ -300,6 +301,29 @@ int mfhex_create(const mfhex_desc *d, void *workspace_dev, size_t workspace_byte
                        "copy vertices")))
         return bail(c);
     if ((c = check_hip(op, hipMemsetAsync(op->bad, 0, 256, s), "hipMemsetAsync"))) return bail(c);
+    {
+        // device basis block: B [Q][P], B^T [P][Q], D [Q][Q], D^T [Q][Q]
+        const int P = op->P, Q = op->Q;
+        std::vector<double> h(basis_len(P, Q));
+        std::vector<float> h32(basis_len(P, Q));
+        for (int a = 0; a < Q; ++a)
+            for (int i = 0; i < P; ++i) {
+                h[a * P + i] = b.B[a * P + i];
+                h[Q * P + i * Q + a] = b.B[a * P + i];
+            }
+        for (int a = 0; a < Q; ++a)
+            for (int k = 0; k < Q; ++k) {
+                h[2 * Q * P + a * Q + k] = b.D[a * Q + k];
+                h[2 * Q * P + Q * Q + k * Q + a] = b.D[a * Q + k];
+            }
+        for (size_t i = 0; i < h.size(); ++i) h32[i] = (float)h[i];
+        if ((c = check_hip(op, hipMemcpy(op->basis64, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice),
+                           "copy basis")))
+            return bail(c);
+        if ((c = check_hip(op, hipMemcpy(op->basis32, h32.data(), h32.size() * sizeof(float), hipMemcpyHostToDevice),
+                           "copy basis")))
+            return bail(c);
+    }
     GeomLaunch g{d->nex, d->ney, d->nez, d->p, d->q, op->vert, &op->basis, s};
     if ((c = check_hip(op, launch_offsets(g, d->dirichlet, op->offsets), "offsets kernel"))) return bail(c);
     if ((c = check_hip(op, launch_qdata(g, d->kind, op->q64, op->q32, op->wdet, op->bad), "qdata kernel")))
@@ -344,18 +368,18 @@ int mfhex_set_kappa(mfhex_op op, const double *kappa_dev, void *stream)
 
 int mfhex_apply(mfhex_op op, int prec, int nrhs, const void *x_dev, void *y_dev, void *stream)
 {
-    return apply_impl(op, prec, nrhs, x_dev, y_dev, static_cast<hipStream_t>(stream), true, 0);
+    return apply_impl(op, prec, nrhs, x_dev, y_dev, static_cast<hipStream_t>(stream), true, -1);
 }
 
 int mfhex_apply_add(mfhex_op op, int prec, int nrhs, const void *x_dev, void *y_dev, void *stream)
 {
-    return apply_impl(op, prec, nrhs, x_dev, y_dev, static_cast<hipStream_t>(stream), false, 0);
+    return apply_impl(op, prec, nrhs, x_dev, y_dev, static_cast<hipStream_t>(stream), false, -1);
 }
 
 int mfhex_apply_adjoint(mfhex_op op, int prec, int nrhs, const void *x_dev, void *y_dev, void *stream)
 {
     // The mass and diffusion operators (and M A M) are symmetric.
-    return apply_impl(op, prec, nrhs, x_dev, y_dev, static_cast<hipStream_t>(stream), true, 0);
+    return apply_impl(op, prec, nrhs, x_dev, y_dev, static_cast<hipStream_t>(stream), true, -1);
 }
 
 int mfhex_kappa_grad(mfhex_op op, const double *u_dev, const double *r_dev, double *g_dev, void *stream)
@@ -366,8 +390,9 @@ int mfhex_kappa_grad(mfhex_op op, const double *u_dev, const double *r_dev, doub
     if (!u_dev || !r_dev || !g_dev) return set_error(op, MFHEX_ERR_ARG, "null vector");
     KgradLaunch a{};
     a.v = view_of(*op, MFHEX_F64);
-    a.basis = &op->basis;
-    a.epb = epb_for(*op, MFHEX_F64, 1);
+    a.P = op->P;
+    a.colloc = op->basis.colloc;
+    a.basis_dev = op->basis64;
     a.u = u_dev;
     a.r = r_dev;
     a.g = g_dev;
@@ -402,13 +427,14 @@ int mfhex_rhs(mfhex_op op, const double *f_dev, double *b_dev, void *stream)
     if (c) return c;
     ApplyLaunch a{};
     a.v = view_of(*op, MFHEX_F64);
-    a.basis = &op->basis;
+    a.P = op->P;
+    a.colloc = op->basis.colloc;
+    a.basis_dev = op->basis64;
     a.prec = MFHEX_F64;
     a.mode = kRhs;
     a.vark = 0;
     a.nvec = 1;
-    a.epb = default_epb(*op, MFHEX_F64, 1);
-    // the load-vector kernel uses a single LDS buffer per element
+    a.variant = 0;
     a.x = f_dev;
     a.y = b_dev;
     a.wdet = wdet;
@@ -427,18 +453,22 @@ int mfhex_tune(mfhex_op op, int prec, int nrhs, void *scratch_dev, const char *c
     return tune(op, prec, nrhs, scratch_dev, cache_path, static_cast<hipStream_t>(stream));
 }
 
-int mfhex_get_config(mfhex_op op, int prec, int nrhs, int32_t *elems_per_block)
+int mfhex_get_config(mfhex_op op, int prec, int nrhs, int32_t *variant, int32_t *elems_per_group,
+                     int32_t *threads_per_group)
 {
-    if (!op || !elems_per_block || nrhs < 1) return fail(MFHEX_ERR_ARG, "bad argument");
-    *elems_per_block = epb_for(*op, prec, nrhs * op->d.ncomp);
+    if (!op || nrhs < 1) return fail(MFHEX_ERR_ARG, "bad argument");
+    const int v = variant_for(*op, prec, nrhs * op->d.ncomp);
+    if (variant) *variant = v;
+    if (elems_per_group) *elems_per_group = variant_g(op->Q, v);
+    if (threads_per_group) *threads_per_group = variant_nt(op->Q, v);
     return MFHEX_OK;
 }
 
-int mfhex_set_config(mfhex_op op, int prec, int nrhs, int32_t elems_per_block)
+int mfhex_set_config(mfhex_op op, int prec, int nrhs, int32_t variant)
 {
     if (!op || nrhs < 1) return fail(MFHEX_ERR_ARG, "bad argument");
-    if (!valid_epb(*op, prec, elems_per_block)) return set_error(op, MFHEX_ERR_ARG, "invalid elements-per-block");
-    op->epb[{prec, nrhs * op->d.ncomp}] = elems_per_block;
+    if (!valid_variant(*op, prec, variant)) return set_error(op, MFHEX_ERR_ARG, "invalid launch variant");
+    op->variant[{prec, nrhs * op->d.ncomp}] = variant;
     return MFHEX_OK;
 }
 

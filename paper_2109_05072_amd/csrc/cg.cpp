@@ -58,7 +58,7 @@ int dot_store(Ctx &ctx, const void *a, int pa, const void *b, int pb, int slot)
 // ||b - A x||^2 in FP64 into sc[kScRRTrue]; r64 / r32 receive the residual when non-null.
 int true_residual(Ctx &ctx, const double *b, const double *x, double *r64, float *r32)
 {
-    TRY(apply_impl(ctx.op, MFHEX_F64, 1, x, ctx.ap64, ctx.s, true, 0));
+    TRY(apply_impl(ctx.op, MFHEX_F64, 1, x, ctx.ap64, ctx.s, true, -1));
     HIP(launch_residual(b, ctx.ap64, r64, r32, ctx.n, ctx.partial, ctx.s), "residual kernel");
     HIP(launch_finalize(ctx.partial, ctx.sc, kFinStore, kScRRTrue, nullptr, 0, ctx.s), "finalize kernel");
     return MFHEX_OK;
@@ -83,7 +83,7 @@ int cg64(Ctx &ctx, const double *b, double *x, const mfhex_cg_opts &o, bool x0_z
     int k = k0;
     int status = MFHEX_ERR_NOCONV;
     while (k < o.maxit) {
-        TRY(apply_impl(ctx.op, MFHEX_F64, 1, ctx.p64, ctx.ap64, ctx.s, true, 0));
+        TRY(apply_impl(ctx.op, MFHEX_F64, 1, ctx.p64, ctx.ap64, ctx.s, true, -1));
         HIP(launch_dot(ctx.p64, MFHEX_F64, ctx.ap64, MFHEX_F64, n, ctx.partial, ctx.s), "dot kernel");
         HIP(launch_finalize(ctx.partial, ctx.sc, kFinAlpha, 0, nullptr, 0, ctx.s), "finalize kernel");
         HIP(launch_update_xr(x, ctx.r64, ctx.p64, ctx.ap64, MFHEX_F64, ctx.sc, n, ctx.partial, ctx.s), "update kernel");
@@ -175,7 +175,7 @@ int cg_solve(mfhex_op op, const double *b, double *x, void *work, const mfhex_cg
         status = MFHEX_ERR_NOCONV;
         bool fallback = false;
         while (iters < o->maxit) {
-            TRY(apply_impl(op, MFHEX_F32, 1, ctx.p32, ctx.ap32, s, true, 0));
+            TRY(apply_impl(op, MFHEX_F32, 1, ctx.p32, ctx.ap32, s, true, -1));
             HIP(launch_dot(ctx.p32, MFHEX_F32, ctx.ap32, MFHEX_F32, n, ctx.partial, s), "dot kernel");
             HIP(launch_finalize(ctx.partial, ctx.sc, kFinAlpha, 0, nullptr, 0, s), "finalize kernel");
             HIP(launch_update_xr(x, ctx.r32, ctx.p32, ctx.ap32, MFHEX_F32, ctx.sc, n, ctx.partial, s), "update kernel");

@@ -15,7 +15,6 @@ constexpr int kMaxP = 9;   // nodes per direction (p = 8)
 constexpr int kMaxQ = 10;  // quadrature points per direction (q = p + 2)
 constexpr int kQdDiff = 6; // symmetric geometric factors per point (Voigt rr, ss, tt, st, rt, rs)
 constexpr int kNumXcd = 8; // MI355X: 8 accelerator complex dies, blocks dealt round-robin
-constexpr int kMaxThreads = 512;  // largest apply block (launch bound of the fused kernels)
 
 // 1D data of one operator, FP64 (host master copy) and FP32.
 struct Basis1D {
@@ -48,12 +47,13 @@ enum Mode : int { kMass = 0, kDiff = 1, kRhs = 2 };
 
 struct ApplyLaunch {
     OpView v;
-    const Basis1D *basis;
+    int P, colloc;
+    const void *basis_dev; // device basis block (B, B^T, D, D^T) in the apply precision
     int prec;             // MFHEX_F64 / MFHEX_F32
     int mode;             // kMass / kDiff / kRhs
     int vark;             // multiply the factors by kappa
     int nvec;
-    int epb;              // elements per block
+    int variant;          // launch variant (elements and threads per group)
     const void *x;        // input (for kRhs: the per-point f, FP64)
     void *y;              // output (accumulated)
     const double *wdet;   // kRhs: w*detJ per point
@@ -62,8 +62,8 @@ struct ApplyLaunch {
 
 struct KgradLaunch {
     OpView v;
-    const Basis1D *basis;
-    int epb;
+    int P, colloc;
+    const double *basis_dev;
     const double *u, *r;
     double *g;
     hipStream_t stream;
@@ -74,6 +74,24 @@ struct KgradLaunch {
 constexpr int lds_pitch(int Q) { return (Q % 2 == 0) ? Q + 1 : Q; }
 constexpr int lds_buf(int Q) { return lds_pitch(Q) * Q * Q; }
 constexpr int apply_nbuf(int mode) { return mode == 1 ? 3 : 1; }
+
+// Launch variants of the fused kernels for q points per direction: G
+// elements per thread group of NT threads; variant 0 is the default.
+constexpr int kNumVariants = 3;
+constexpr int variant_g(int Q, int v)
+{
+    return Q <= 3 ? (v == 0 ? 8 : v == 1 ? 4 : 16)
+         : Q <= 4 ? (v == 0 ? 4 : v == 1 ? 2 : 8)
+         : Q <= 6 ? (v == 0 ? 2 : v == 1 ? 4 : 1)
+         : Q <= 8 ? (v == 0 ? 1 : v == 1 ? 2 : 1)
+                  : (v == 0 ? 1 : v == 1 ? 1 : 2);
+}
+constexpr int variant_nt(int Q, int v)
+{
+    return Q <= 6 ? 64 : Q <= 8 ? (v == 2 ? 128 : 64) : (v == 0 ? 64 : 128);
+}
+// Size of the device basis block in elements: B, B^T (q x p+1 each), D, D^T (q x q each).
+constexpr int basis_len(int P, int Q) { return 2 * Q * P + 2 * Q * Q; }
 
 // Per-order dispatch (one translation unit per order, apply_p<N>.hip).
 hipError_t launch_apply(const ApplyLaunch &a);

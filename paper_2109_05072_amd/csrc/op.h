@@ -21,8 +21,10 @@ struct mfhex_op_s {
     double *kappa = nullptr;
     double *wdet = nullptr;
     int32_t *bad = nullptr;
+    double *basis64 = nullptr;  // device basis block, FP64 and FP32
+    float *basis32 = nullptr;
     bool kappa_set = false;
-    std::map<std::pair<int, int>, int> epb;  // (prec, nvec) -> elements per block
+    std::map<std::pair<int, int>, int> variant;  // (prec, nvec) -> launch variant
     std::string err;
     double *pinned = nullptr;  // small pinned host buffer for solver scalars
 };
@@ -31,7 +33,7 @@ namespace mfhex {
 
 // Workspace layout (byte offsets, 256-aligned); absent parts are SIZE_MAX.
 struct Layout {
-    size_t vert, offsets, q64, q32, kappa, wdet, bad, total;
+    size_t vert, offsets, q64, q32, kappa, wdet, basis, bad, total;
 };
 Layout workspace_layout(const mfhex_desc &d, int64_t E, int P, int Q);
 
@@ -46,10 +48,10 @@ int set_error(mfhex_op op, int code, const std::string &msg);
 int check_hip(mfhex_op op, hipError_t e, const char *what);
 
 // Internal apply: y (+)= A x on `s` with an explicit configuration.
-int apply_impl(mfhex_op op, int prec, int nrhs, const void *x, void *y, hipStream_t s, bool zero, int epb_override);
-int default_epb(const mfhex_op_s &op, int prec, int nvec);
-bool valid_epb(const mfhex_op_s &op, int prec, int epb);
-int epb_for(const mfhex_op_s &op, int prec, int nvec);
+int apply_impl(mfhex_op op, int prec, int nrhs, const void *x, void *y, hipStream_t s, bool zero, int variant);
+int default_variant(const mfhex_op_s &op, int prec, int nvec);
+bool valid_variant(const mfhex_op_s &op, int prec, int variant);
+int variant_for(const mfhex_op_s &op, int prec, int nvec);
 int mode_of(const mfhex_op_s &op);
 
 int cg_solve(mfhex_op op, const double *b, double *x, void *work, const mfhex_cg_opts *o, mfhex_cg_stats *st,

@@ -1,12 +1,12 @@
 // Autotuner for the fused apply: per (operator, precision, number of vectors)
-// pick the elements-per-block of the launch by measurement.
+// pick the launch variant (elements and threads per group) by measurement.
 //
 // Every candidate is first checked against the default configuration on a
 // random input (max-norm relative difference <= 1e-13 in FP64, 1e-5 in FP32;
-// candidates only change the grouping of elements into blocks, so anything
+// candidates only change the grouping of elements and lanes, so anything
 // larger is a bug and the candidate is dropped), then timed with HIP events
 // over repeated applies.  The winner is kept on the handle and appended to a
-// text cache "<arch> kind quad p nvec prec epb", which later handles read
+// text cache "<arch> kind quad p nvec prec variant", which later handles read
 // from the file named by MFHEX_TUNE_CACHE.  This plays the role of the
 // offline benchmark sweeps that select kernel variants per problem shape
 // (Sec. 2, the MAGMA batched kernels chosen from tuning tables).
@@ -44,8 +44,8 @@ void load_tune_cache(mfhex_op op)
     char a[64];
     int kind, quad, p, nvec, prec, epb;
     while (std::fscanf(f, "%63s %d %d %d %d %d %d", a, &kind, &quad, &p, &nvec, &prec, &epb) == 7) {
-        if (arch == a && kind == op->d.kind && quad == op->d.quad && p == op->d.p && valid_epb(*op, prec, epb))
-            op->epb[{prec, nvec}] = epb;
+        if (arch == a && kind == op->d.kind && quad == op->d.quad && p == op->d.p && valid_variant(*op, prec, epb))
+            op->variant[{prec, nvec}] = epb;
     }
     std::fclose(f);
 }
@@ -74,11 +74,11 @@ int tune(mfhex_op op, int prec, int nrhs, void *scratch, const char *cache_path,
         if ((c = check_hip(op, launch_copy(x64, MFHEX_F64, ytest, MFHEX_F32, len, s), "copy kernel"))) return cleanup(c);
         if ((c = check_hip(op, hipMemcpyAsync(x64, ytest, len * es, hipMemcpyDeviceToDevice, s), "copy"))) return cleanup(c);
     }
-    const int def = default_epb(*op, prec, nvec);
+    const int def = default_variant(*op, prec, nvec);
     if ((c = apply_impl(op, prec, nrhs, x, yref, s, true, def))) return cleanup(c);
     std::vector<int> cand;
-    for (int e = 1; e * op->Q * op->Q <= kMaxThreads; ++e)
-        if (valid_epb(*op, prec, e)) cand.push_back(e);
+    for (int e = 0; e < kNumVariants; ++e)
+        if (valid_variant(*op, prec, e)) cand.push_back(e);
     hipEvent_t e0, e1;
     if ((c = check_hip(op, hipEventCreate(&e0), "hipEventCreate"))) return cleanup(c);
     if ((c = check_hip(op, hipEventCreate(&e1), "hipEventCreate"))) return cleanup(c);
@@ -108,7 +108,7 @@ int tune(mfhex_op op, int prec, int nrhs, void *scratch, const char *cache_path,
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (c) return cleanup(c);
-    op->epb[{prec, nvec}] = best;
+    op->variant[{prec, nvec}] = best;
     if (cache_path && *cache_path) {
         FILE *f = std::fopen(cache_path, "a");
         if (f) {

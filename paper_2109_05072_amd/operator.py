@@ -176,15 +176,16 @@ class Operator:
                         st.rel_resid_rec, st.seconds, hist[: min(st.iters, 8191) + 1])
 
     # -- tuning ------------------------------------------------------------------------------
-    def tune(self, dtype=torch.float64, nrhs: int = 1, cache_path: Optional[str] = None) -> int:
+    def tune(self, dtype=torch.float64, nrhs: int = 1, cache_path: Optional[str] = None):
         n = self.n_nodes * nrhs * self.ncomp
         scratch = torch.empty(L.tune_scratch_bytes(n) + 256, dtype=torch.uint8, device=self.device)
         ptr = (scratch.data_ptr() + 255) & ~255
         L.mfhex_tune(self.handle, _prec(dtype), nrhs, ptr, cache_path, _stream())
         return self.get_config(dtype, nrhs)
 
-    def get_config(self, dtype=torch.float64, nrhs: int = 1) -> int:
+    def get_config(self, dtype=torch.float64, nrhs: int = 1):
+        """(variant, elements per group, threads per group) of the apply launch."""
         return L.mfhex_get_config(self.handle, _prec(dtype), nrhs)
 
-    def set_config(self, elems_per_block: int, dtype=torch.float64, nrhs: int = 1) -> None:
-        L.mfhex_set_config(self.handle, _prec(dtype), nrhs, elems_per_block)
+    def set_config(self, variant: int, dtype=torch.float64, nrhs: int = 1) -> None:
+        L.mfhex_set_config(self.handle, _prec(dtype), nrhs, variant)

@@ -47,9 +47,12 @@ def test_query_sizes():
     assert s.n_nodes == 7 * 5 * 9
     assert s.n_elem == 24
     assert s.n_qpts == 24 * 64
-    # vertices + offsets + FP64 and FP32 factors + flag, each 256-aligned
+    # vertices + offsets + FP64 and FP32 factors + 1D basis block (B, B^T, D, D^T in FP64
+    # and FP32) + flag, each 256-aligned
     al = lambda x: (x + 255) // 256 * 256  # noqa: E731
-    expect = al(4 * 3 * 5 * 3 * 8) + al(24 * 27 * 4) + al(24 * 6 * 64 * 8) + al(24 * 6 * 64 * 4) + 256
+    nb = 2 * 4 * 3 + 2 * 4 * 4
+    expect = (al(4 * 3 * 5 * 3 * 8) + al(24 * 27 * 4) + al(24 * 6 * 64 * 8) + al(24 * 6 * 64 * 4)
+              + al(nb * 12 + 256) + 256)
     assert s.workspace_bytes == expect
     assert s.cg_work_bytes >= s.n_nodes * (3 * 8 + 3 * 4)
 
