@@ -62,13 +62,15 @@ def cpu_baseline(p: int, budget_s: float = 12.0) -> dict:
 
     ne = 2
     n, t = run(ne)
-    # grow the mesh until one apply takes a sizeable part of the budget
-    while t < budget_s / 8 and ne < 64:
+    # grow the mesh until one apply takes about a quarter of the budget, then time three applies
+    while t < budget_s / 5 and ne < 96:
         ne = max(ne + 1, int(ne * min(2.0, (budget_s / 4 / max(t, 1e-3)) ** (1 / 3))))
         n, t = run(ne)
+    ts = sorted([t] + [run(ne)[1] for _ in range(2)])
+    t = ts[1]
     return {"value": n / t / 1e9, "unit": "GDOF/s", "cores": cores, "kind": "oracle",
-            "sample": f"BP3 FP64 apply, p={p}, q={p + 2}, {ne}^3 elements ({n} DOFs), one apply, "
-                      f"{t:.2f} s, dense-tabulation oracle, OpenMP {cores} threads"}
+            "sample": f"BP3 FP64 apply, p={p}, q={p + 2}, {ne}^3 elements ({n} DOFs), median of 3 applies "
+                      f"({t:.2f} s each), dense-tabulation oracle, OpenMP {cores} threads"}
 
 
 def main():
@@ -80,7 +82,11 @@ def main():
     ap.add_argument("--dofs", type=float, default=1e7)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cg", action="store_true", help="also time FP64 vs mixed CG to 1e-10")
-    ap.add_argument("--tune", action="store_true", help="autotune elements-per-block before timing")
+    ap.add_argument("--tune", action="store_true", help="autotune the launch variant before timing")
+    ap.add_argument("--sweep", action="store_true", help="report the time of every launch variant (stderr)")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="after timing, copy 1 GiB device-to-device twice (a kernel of known traffic, "
+                         "used to scale the HBM byte counters)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -101,6 +107,8 @@ def main():
         op = mf.Operator(ne, ne, ne, p, vert, kind="diffusion", quad="gauss", dirichlet=True)
         x = torch.from_numpy(synth.uniform_vector(op.n_nodes)).cuda()
         ops[p], xs[p], ys[p] = op, x, torch.empty_like(x)
+        if args.sweep:
+            sweep_variants(op, x, p)
         if args.tune:
             op.tune()
         meta[p] = dict(ne=ne, N=op.n_nodes, E=op.n_elem, q=p + 2, epb=op.get_config())
@@ -142,6 +150,11 @@ def main():
                                  "threads_per_group": m["epb"][2]},
                       "paper_v100_cuda_gen_gdofs": PAPER_V100_CUDA_GEN.get(p)})
     dom = max(per_p, key=lambda r: r["ms"])
+    from paper_2109_05072_amd.prof_summary import read_traffic
+    traffic = read_traffic(os.path.join(ROOT, "profiles", "bp3_apply_traffic.txt"))
+    lg = dom["launch"]
+    dom_name = (f"k_apply p={dom['p']} q={dom['p'] + 2} diffusion double G={lg['elements_per_group']} "
+                f"NT={lg['threads_per_group']}")
     out = {
         "metric": METRIC, "value": round(value, 3), "unit": "GDOF/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
@@ -150,16 +163,42 @@ def main():
         "config": {"workload": f"BP3 diffusion apply FP64, Gauss q=p+2, p={','.join(map(str, orders))}, "
                                f"~{args.dofs:.0e} DOFs per order, perturbed hex mesh, Dirichlet",
                    "orders": orders, "dofs_per_step": dofs_per_step},
-        "roofline": {"bound": "hbm", "kernel": f"k_apply BP3 p={dom['p']} (q={dom['p'] + 2}) FP64",
+        "roofline": {"bound": "hbm", "kernel": dom_name,
                      "achieved": dom["alg_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": dom["hbm_frac"], "traffic": None},
+                     "frac": dom["hbm_frac"], "traffic": traffic.get(dom_name),
+                     "alg_bytes_per_launch": dom["alg_bytes"]},
         "per_order": per_p,
     }
+    if args.calib_copy:
+        a = torch.empty(1 << 27, dtype=torch.float64, device="cuda").fill_(1.0)
+        b = torch.empty_like(a)
+        for _ in range(2):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     if args.cg:
         out["cg"] = cg_compare()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(dom["p"])
     print(json.dumps(out), flush=True)
+
+
+def sweep_variants(op, x, p, reps=10):
+    import torch
+    y = torch.empty_like(x)
+    res = []
+    for v in range(5):
+        op.set_config(v)
+        op.apply(x, y)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            op.apply(x, y)
+        e1.record()
+        torch.cuda.synchronize()
+        res.append((v, op.get_config()[1:], round(e0.elapsed_time(e1) / reps, 4)))
+    op.set_config(0)
+    print(f"# sweep p={p}: " + "  ".join(f"v{v} {g}: {ms} ms" for v, g, ms in res), file=sys.stderr, flush=True)
 
 
 def cg_compare(orders=(3,), dofs=3e7):

@@ -106,8 +106,8 @@ __device__ __forceinline__ void contract(const T *src, T *dst, const T *__restri
             for (int i = 0; i < NI; ++i) v[r][i] = src[base[r] + i * ST];
         }
     }
-    // rows in flight per scalar-load wait: about 16 coefficients
-    constexpr int UR = NI >= 16 ? 1 : 16 / NI;
+    // coefficient rows in flight per scalar-load wait: at least two, about 24 coefficients
+    constexpr int UR = NI >= 12 ? 2 : 24 / NI;
 #pragma unroll UR
     for (int o = 0; o < NO; ++o) {
         const T *row = M + o * NI;
@@ -390,6 +390,8 @@ static hipError_t launch_apply_t(const ApplyLaunch &a)
     case 0: return launch_apply_v<P, Q, COLLOC, MODE, VARK, T, variant_g(Q, 0), variant_nt(Q, 0)>(a);
     case 1: return launch_apply_v<P, Q, COLLOC, MODE, VARK, T, variant_g(Q, 1), variant_nt(Q, 1)>(a);
     case 2: return launch_apply_v<P, Q, COLLOC, MODE, VARK, T, variant_g(Q, 2), variant_nt(Q, 2)>(a);
+    case 3: return launch_apply_v<P, Q, COLLOC, MODE, VARK, T, variant_g(Q, 3), variant_nt(Q, 3)>(a);
+    case 4: return launch_apply_v<P, Q, COLLOC, MODE, VARK, T, variant_g(Q, 4), variant_nt(Q, 4)>(a);
     default: return hipErrorInvalidValue;
     }
 }

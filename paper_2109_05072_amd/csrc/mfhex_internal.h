@@ -77,19 +77,17 @@ constexpr int apply_nbuf(int mode) { return mode == 1 ? 3 : 1; }
 
 // Launch variants of the fused kernels for q points per direction: G
 // elements per thread group of NT threads; variant 0 is the default.
-constexpr int kNumVariants = 3;
-constexpr int variant_g(int Q, int v)
-{
-    return Q <= 3 ? (v == 0 ? 8 : v == 1 ? 4 : 16)
-         : Q <= 4 ? (v == 0 ? 4 : v == 1 ? 2 : 8)
-         : Q <= 6 ? (v == 0 ? 2 : v == 1 ? 4 : 1)
-         : Q <= 8 ? (v == 0 ? 1 : v == 1 ? 2 : 1)
-                  : (v == 0 ? 1 : v == 1 ? 1 : 2);
-}
-constexpr int variant_nt(int Q, int v)
-{
-    return Q <= 6 ? 64 : Q <= 8 ? (v == 2 ? 128 : 64) : (v == 0 ? 64 : 128);
-}
+constexpr int kNumVariants = 5;
+// rows: Q = 2 .. 10; variant 0 is the measured best on MI355X (BP3 FP64, 1e7 nodes)
+constexpr int kVarG[9][kNumVariants] = {
+    {16, 8, 32, 16, 32}, {8, 4, 16, 8, 16}, {4, 2, 8, 4, 8}, {4, 2, 1, 2, 4}, {2, 2, 1, 4, 1},
+    {1, 1, 2, 2, 1},     {1, 1, 2, 2, 1},   {1, 1, 2, 1, 2}, {1, 1, 2, 1, 2}};
+constexpr int kVarNT[9][kNumVariants] = {
+    {64, 64, 64, 128, 128},  {64, 64, 64, 128, 128},  {64, 64, 64, 128, 128},
+    {128, 64, 64, 128, 64},  {128, 64, 64, 128, 128}, {128, 64, 64, 128, 256},
+    {128, 64, 64, 128, 256}, {128, 64, 128, 256, 256}, {128, 64, 128, 256, 256}};
+constexpr int variant_g(int Q, int v) { return kVarG[Q - 2][v]; }
+constexpr int variant_nt(int Q, int v) { return kVarNT[Q - 2][v]; }
 // Size of the device basis block in elements: B, B^T (q x p+1 each), D, D^T (q x q each).
 constexpr int basis_len(int P, int Q) { return 2 * Q * P + 2 * Q * Q; }
 

@@ -1,0 +1,128 @@
+"""Summaries of rocprofv3 output for the fused apply kernels.
+
+``python -m paper_2109_05072_amd.prof_summary trace <dir> <command...>``
+    kernel-trace statistics (``*_kernel_stats.csv``) -> text table.
+``python -m paper_2109_05072_amd.prof_summary traffic <fetch_dir> <write_dir> <command...>``
+    FETCH_SIZE / WRITE_SIZE per dispatch of each apply kernel, scaled by what
+    the same counters read for the 1 GiB device-to-device copy that
+    ``bench.py --calib-copy`` runs (the copy reads and writes exactly 2^30
+    bytes), -> HBM bytes per launch.  The kernel source hash is recorded so
+    that a later reader can tell whether the numbers still describe the
+    current kernels.
+
+The benchmark reads the traffic summary back (``read_traffic``) and reports
+it only while the source hash matches.
+"""
+from __future__ import annotations
+
+import csv
+import glob
+import hashlib
+import os
+import re
+import sys
+from collections import defaultdict
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+KERNEL_SOURCES = ("csrc/apply_kernels.hpp", "csrc/mfhex_internal.h")
+COPY_BYTES = 1 << 30
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(HERE, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def _short(name: str) -> str:
+    m = re.match(r"void mfhex::k_apply<(\d+), (\d+), (\w+), (\d), (\w+), (\w+), (\d+), (\d+)>", name)
+    if m:
+        P, Q, colloc, mode, vark, T, G, NT = m.groups()
+        kind = {"0": "mass", "1": "diffusion", "2": "rhs"}[mode]
+        return f"k_apply p={int(P) - 1} q={Q} {kind}{' kappa' if vark == 'true' else ''} {T} G={G} NT={NT}"
+    name = name.replace("(anonymous namespace)::", "").replace("void ", "")
+    return name.split("(")[0].split("<")[0].split("::")[-1][:60]
+
+
+def _find(d: str, suffix: str) -> str:
+    fs = glob.glob(os.path.join(d, "**", "*" + suffix), recursive=True)
+    if not fs:
+        raise FileNotFoundError(f"no *{suffix} under {d}")
+    return fs[0]
+
+
+def trace_summary(d: str, command: str) -> str:
+    rows = list(csv.DictReader(open(_find(d, "kernel_stats.csv"))))
+    out = [f"# rocprofv3 kernel trace summary", f"# command: {command}",
+           f"# kernel source hash: {kernel_source_hash()}",
+           f"{'kernel':<60} {'calls':>6} {'avg_us':>10} {'min_us':>10} {'max_us':>10} {'pct':>6}"]
+    for r in rows:
+        out.append(f"{_short(r['Name']):<60} {int(r['Calls']):>6} {float(r['AverageNs']) / 1e3:>10.2f} "
+                   f"{float(r['MinNs']) / 1e3:>10.2f} {float(r['MaxNs']) / 1e3:>10.2f} "
+                   f"{float(r['Percentage']):>6.2f}")
+    return "\n".join(out) + "\n"
+
+
+def _counter(d: str, counter: str):
+    per = defaultdict(list)
+    dur = defaultdict(list)
+    for r in csv.DictReader(open(_find(d, "counter_collection.csv"))):
+        if r["Counter_Name"] != counter:
+            continue
+        per[r["Kernel_Name"]].append(float(r["Counter_Value"]))
+        dur[r["Kernel_Name"]].append(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
+    return per, dur
+
+
+def traffic_summary(fetch_dir: str, write_dir: str, command: str) -> str:
+    fe, fdur = _counter(fetch_dir, "FETCH_SIZE")
+    wr, _ = _counter(write_dir, "WRITE_SIZE")
+    copy = [k for k in fe if "copyBuffer" in k or "copy" in k.lower()]
+    # the calibration copy is the dispatch with by far the largest fetch among the copy kernels
+    cf = max(v for k in copy for v in fe[k])
+    cw = max(v for k in copy if k in wr for v in wr[k])
+    f_scale = COPY_BYTES / (cf * 1024.0)
+    w_scale = COPY_BYTES / (cw * 1024.0)
+    out = [f"# HBM traffic per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE (KiB per dispatch)",
+           f"# command: {command}",
+           f"# kernel source hash: {kernel_source_hash()}",
+           f"# calibration: 1 GiB device copy reads FETCH_SIZE={cf:.1f} KiB, WRITE_SIZE={cw:.1f} KiB -> "
+           f"scale fetch x{f_scale:.4f}, write x{w_scale:.4f}",
+           f"{'kernel':<60} {'fetch_KiB':>12} {'write_KiB':>12} {'traffic_bytes':>15} {'avg_us':>9}"]
+    for k in fe:
+        if "k_apply" not in k or k not in wr:
+            continue
+        f = sum(fe[k]) / len(fe[k])
+        w = sum(wr[k]) / len(wr[k])
+        t = f * 1024 * f_scale + w * 1024 * w_scale
+        out.append(f"{_short(k):<60} {f:>12.1f} {w:>12.1f} {t:>15.0f} {sum(fdur[k]) / len(fdur[k]) / 1e3:>9.2f}")
+    return "\n".join(out) + "\n"
+
+
+def read_traffic(path: str):
+    """{short kernel name: traffic bytes} if the summary matches the current kernel sources, else {}."""
+    if not os.path.exists(path):
+        return {}
+    txt = open(path).read()
+    m = re.search(r"kernel source hash: (\w+)", txt)
+    if not m or m.group(1) != kernel_source_hash():
+        return {}
+    res = {}
+    for line in txt.splitlines():
+        if line.startswith("k_apply"):
+            parts = line.split()
+            name = " ".join(parts[:-4])
+            res[name] = float(parts[-2])
+    return res
+
+
+if __name__ == "__main__":
+    mode = sys.argv[1]
+    if mode == "trace":
+        sys.stdout.write(trace_summary(sys.argv[2], " ".join(sys.argv[3:])))
+    elif mode == "traffic":
+        sys.stdout.write(traffic_summary(sys.argv[2], sys.argv[3], " ".join(sys.argv[4:])))
+    else:
+        raise SystemExit("usage: prof_summary trace <dir> <cmd...> | traffic <fetch_dir> <write_dir> <cmd...>")

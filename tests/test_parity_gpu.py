@@ -58,7 +58,7 @@ def host(t):
 
 def ragged_variant(op, dtype=torch.float64):
     """A launch variant whose group size does not divide the element count."""
-    for v in range(3):
+    for v in range(5):
         op.set_config(v, dtype)
         g = op.get_config(dtype)[1]
         if op.n_elem % g and op.n_elem > g:
@@ -79,7 +79,7 @@ def test_apply_fp64_matches_oracle(gpu_lib, p, kind, quad, dirichlet):
     yo = oracle.apply(pr, x)
     y = host(op.apply(dev(x)))
     assert relerr(y, yo) <= TOL64
-    for v in range(3):
+    for v in range(5):
         op.set_config(v)
         _say("apply64 variant", v, op.get_config())
         y2 = host(op.apply(dev(x)))
@@ -188,13 +188,13 @@ def test_every_launch_configuration_agrees(gpu_lib, p, quad, nrhs):
     op, pr = build(gpu_lib, 4, 3, 3, p, "diffusion", quad)
     x = dev(synth.uniform_vector(pr.n_nodes, nvec=nrhs))
     ref = host(op.apply(x))
-    for v in range(3):
+    for v in range(5):
         op.set_config(v, nrhs=nrhs)
         assert relerr(host(op.apply(x)), ref) <= 1e-13
     with pytest.raises(L.MFHexError):
-        op.set_config(3, nrhs=nrhs)
+        op.set_config(5, nrhs=nrhs)
     best = op.tune(nrhs=nrhs)
-    assert best[0] in (0, 1, 2)
+    assert best[0] in range(5)
     assert relerr(host(op.apply(x)), ref) <= 1e-13
 
 
