@@ -41,9 +41,12 @@ def alg_bytes(N: int, E: int, p: int, q: int, g: int = 6, s: int = 8, nvec: int 
     return s * N * nvec * 2 + 4 * E * (p + 1) ** 3 + s * g * E * q ** 3
 
 
-def alg_flops(E: int, p: int, q: int) -> int:
+def alg_flops(E: int, p: int, q: int, kind: str = "diffusion", colloc: bool = False) -> int:
     P, Q = p + 1, q
-    return E * (4 * (Q * P ** 3 + Q * Q * P * P + Q ** 3 * P) + 12 * Q ** 4 + 15 * Q ** 3)
+    interp = 0 if colloc else 4 * (Q * P ** 3 + Q * Q * P * P + Q ** 3 * P)
+    if kind == "mass":
+        return E * (interp + Q ** 3)
+    return E * (interp + 12 * Q ** 4 + 15 * Q ** 3)
 
 
 def cpu_baseline(p: int, budget_s: float = 12.0) -> dict:
@@ -80,6 +83,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--orders", type=str, default="3,4,5,6,7,8")
     ap.add_argument("--dofs", type=float, default=1e7)
+    ap.add_argument("--kind", choices=["diffusion", "mass"], default="diffusion",
+                    help="diffusion = BP3 (default), mass = BP1")
+    ap.add_argument("--batched", action="store_true",
+                    help="also time the batched collocated apply (BP5 / BP6, 4/8/32 right-hand sides)")
+    ap.add_argument("--adjoint", action="store_true",
+                    help="also time the variable-coefficient forward / backward (p=4, 1e7 DOFs)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cg", action="store_true", help="also time FP64 vs mixed CG to 1e-10")
     ap.add_argument("--tune", action="store_true", help="autotune the launch variant before timing")
@@ -104,7 +113,7 @@ def main():
     for p in orders:
         ne = synth.elems_for_dofs(args.dofs, p)
         vert = synth.mesh_vertices(ne, ne, ne)
-        op = mf.Operator(ne, ne, ne, p, vert, kind="diffusion", quad="gauss", dirichlet=True)
+        op = mf.Operator(ne, ne, ne, p, vert, kind=args.kind, quad="gauss", dirichlet=(args.kind == "diffusion"))
         x = torch.from_numpy(synth.uniform_vector(op.n_nodes)).cuda()
         ops[p], xs[p], ys[p] = op, x, torch.empty_like(x)
         if args.sweep:
@@ -140,12 +149,12 @@ def main():
     for p in orders:
         t_ms = float(np.mean([a.elapsed_time(b) for a, b in evs[p]]))
         m = meta[p]
-        byts = alg_bytes(m["N"], m["E"], p, m["q"])
+        byts = alg_bytes(m["N"], m["E"], p, m["q"], g=6 if args.kind == "diffusion" else 1)
         gbs = byts / (t_ms / 1e3) / 1e9
         per_p.append({"p": p, "elements_per_dim": m["ne"], "dofs": m["N"], "ms": round(t_ms, 4),
                       "gdofs": round(m["N"] / (t_ms / 1e3) / 1e9, 3), "alg_bytes": byts,
                       "alg_gbs": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
-                      "alg_tflops": round(alg_flops(m["E"], p, m["q"]) / (t_ms / 1e3) / 1e12, 2),
+                      "alg_tflops": round(alg_flops(m["E"], p, m["q"], args.kind) / (t_ms / 1e3) / 1e12, 2),
                       "launch": {"variant": m["epb"][0], "elements_per_group": m["epb"][1],
                                  "threads_per_group": m["epb"][2]},
                       "paper_v100_cuda_gen_gdofs": PAPER_V100_CUDA_GEN.get(p)})
@@ -153,15 +162,18 @@ def main():
     from paper_2109_05072_amd.prof_summary import read_traffic
     traffic = read_traffic(os.path.join(ROOT, "profiles", "bp3_apply_traffic.txt"))
     lg = dom["launch"]
-    dom_name = (f"k_apply p={dom['p']} q={dom['p'] + 2} diffusion double G={lg['elements_per_group']} "
+    dom_name = (f"k_apply p={dom['p']} q={dom['p'] + 2} {args.kind} double G={lg['elements_per_group']} "
                 f"NT={lg['threads_per_group']}")
     out = {
         "metric": METRIC, "value": round(value, 3), "unit": "GDOF/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
         "data": "synthetic (seeded perturbed unit-cube hex meshes, U[-1,1] inputs)",
-        "config": {"workload": f"BP3 diffusion apply FP64, Gauss q=p+2, p={','.join(map(str, orders))}, "
-                               f"~{args.dofs:.0e} DOFs per order, perturbed hex mesh, Dirichlet",
+        "config": {"workload": (f"BP3 diffusion apply FP64, Gauss q=p+2, p={','.join(map(str, orders))}, "
+                                f"~{args.dofs:.0e} DOFs per order, perturbed hex mesh, Dirichlet")
+                   if args.kind == "diffusion" else
+                               (f"BP1 mass apply FP64, Gauss q=p+2, p={','.join(map(str, orders))}, "
+                                f"~{args.dofs:.0e} DOFs per order, perturbed hex mesh"),
                    "orders": orders, "dofs_per_step": dofs_per_step},
         "roofline": {"bound": "hbm", "kernel": dom_name,
                      "achieved": dom["alg_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -176,19 +188,31 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         del a, b
+    for p in orders:
+        ops[p].close()
+    del ops, xs, ys
+    torch.cuda.empty_cache()
     if args.cg:
         out["cg"] = cg_compare()
+    if args.batched:
+        out["batched"] = batched_sweep()
+    if args.adjoint:
+        out["adjoint"] = adjoint_bench()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(dom["p"])
     print(json.dumps(out), flush=True)
 
 
-def sweep_variants(op, x, p, reps=10):
+def sweep_variants(op, x, p, reps=10, nrhs=1):
     import torch
     y = torch.empty_like(x)
     res = []
-    for v in range(5):
-        op.set_config(v)
+    import paper_2109_05072_amd as mf
+    for v in range(9):
+        try:
+            op.set_config(v, nrhs=nrhs)
+        except mf.MFHexError:
+            continue
         op.apply(x, y)
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
@@ -196,12 +220,114 @@ def sweep_variants(op, x, p, reps=10):
             op.apply(x, y)
         e1.record()
         torch.cuda.synchronize()
-        res.append((v, op.get_config()[1:], round(e0.elapsed_time(e1) / reps, 4)))
-    op.set_config(0)
-    print(f"# sweep p={p}: " + "  ".join(f"v{v} {g}: {ms} ms" for v, g, ms in res), file=sys.stderr, flush=True)
+        res.append((v, op.get_config(nrhs=nrhs)[1:], round(e0.elapsed_time(e1) / reps, 4)))
+    op.set_config(0, nrhs=nrhs)
+    print(f"# sweep p={p} nrhs={nrhs}: " + "  ".join(f"v{v} {g}: {ms} ms" for v, g, ms in res), file=sys.stderr,
+          flush=True)
 
 
-def cg_compare(orders=(3,), dofs=3e7):
+def _time(fn, reps=5):
+    import torch
+    fn()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def batched_sweep(orders=(3, 4, 5, 6, 7, 8), dofs=3e7, ncomps=(1, 3), nrhss=(4, 8, 32)):
+    """Collocated (Gauss-Lobatto q=p+1) diffusion, BP5 (ncomp=1) and BP6 (ncomp=3), several
+    right-hand sides per launch, autotuned launch variant; throughput in field-DOF/s."""
+    import torch
+    import synth
+    import paper_2109_05072_amd as mf
+    res = []
+    for p in orders:
+        ne = synth.elems_for_dofs(dofs, p)
+        vert = synth.mesh_vertices(ne, ne, ne)
+        for nc in ncomps:
+            op = mf.Operator(ne, ne, ne, p, vert, kind="diffusion", quad="gll", ncomp=nc, dirichlet=True)
+            for nr in nrhss:
+                nvec = nc * nr
+                x = torch.rand(op.n_nodes, nvec, dtype=torch.float64, device="cuda") * 2 - 1
+                y = torch.empty_like(x)
+                if os.environ.get("MFHEX_BENCH_SWEEP"):
+                    sweep_variants(op, x, p, reps=3, nrhs=nr)
+                variant = op.tune(nrhs=nr)
+                ms = _time(lambda: op.apply(x, y), reps=3)
+                byts = alg_bytes(op.n_nodes, op.n_elem, p, p + 1, nvec=nvec)
+                fl = alg_flops(op.n_elem, p, p + 1, colloc=True) * nvec
+                res.append({"p": p, "ncomp": nc, "nrhs": nr, "dofs_per_field": op.n_nodes, "ms": round(ms, 3),
+                            "gdofs_fields": round(op.n_nodes * nvec / (ms / 1e3) / 1e9, 2),
+                            "alg_gbs": round(byts / (ms / 1e3) / 1e9, 1),
+                            "hbm_frac": round(byts / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+                            "alg_tflops": round(fl / (ms / 1e3) / 1e12, 2), "variant": list(variant)})
+                print(f"# batched {res[-1]}", file=sys.stderr, flush=True)
+                del x, y
+                torch.cuda.empty_cache()
+            op.close()
+            del op
+            torch.cuda.empty_cache()
+    return res
+
+
+def adjoint_bench(p=4, dofs=1e7):
+    """Variable-coefficient diffusion y = A(kappa) u and the backward of 0.5||y - f||^2 (grad wrt
+    u and kappa), p=4, q=6, about 1e7 DOFs; checked by central differences (exact: the loss is
+    quadratic in kappa and in u)."""
+    import numpy as np
+    import torch
+    import synth
+    import paper_2109_05072_amd as mf
+    from paper_2109_05072_amd.autograd import diffusion
+    ne = synth.elems_for_dofs(dofs, p)
+    vert = synth.mesh_vertices(ne, ne, ne)
+    op = mf.Operator(ne, ne, ne, p, vert, kind="diffusion", quad="gauss", dirichlet=True, variable_kappa=True)
+    kap = torch.from_numpy(synth.kappa_field(op.qpoint_coords().cpu().numpy())).cuda()
+    n = op.n_nodes
+    nn = p * ne + 1
+    ijk = np.arange(n)
+    ix, iy, iz = ijk % nn, (ijk // nn) % nn, ijk // (nn * nn)
+    interior = ((ix > 0) & (ix < nn - 1) & (iy > 0) & (iy < nn - 1) & (iz > 0) & (iz < nn - 1)).astype(float)
+    u = torch.from_numpy(synth.uniform_vector(n, seed=1)).cuda()
+    f = torch.from_numpy(synth.uniform_vector(n, seed=2) * interior).cuda()
+    uu = u.clone().requires_grad_(True)
+    kk = kap.clone().requires_grad_(True)
+
+    def loss(a, b):
+        r = diffusion(a, b, op) - f
+        return 0.5 * (r * r).sum()
+
+    fwd_ms = _time(lambda: op.set_kappa(kap) or op.apply(u), reps=5)
+    r = op.apply(u) - f
+    bwd_ms = _time(lambda: (op.apply_adjoint(r), op.kappa_grad(u, r)), reps=5)
+    kg_ms = _time(lambda: op.kappa_grad(u, r), reps=5)
+    Lv = loss(uu, kk)
+    gu, gk = torch.autograd.grad(Lv, [uu, kk])
+    rng = np.random.default_rng(synth.SEED_DIR)
+    fd = []
+    with torch.no_grad():
+        for _ in range(2):
+            d = torch.from_numpy(rng.standard_normal(tuple(kap.shape))).cuda()
+            eps = 1e-2 * float(kap.norm() / d.norm())
+            num = float((loss(u, kap + eps * d) - loss(u, kap - eps * d)) / (2 * eps))
+            an = float((gk * d).sum())
+            fd.append({"wrt": "kappa", "rel_err": abs(num - an) / abs(an)})
+            du = torch.from_numpy(rng.standard_normal(n)).cuda()
+            eps = 1e-2 * float(u.norm() / du.norm())
+            num = float((loss(u + eps * du, kap) - loss(u - eps * du, kap)) / (2 * eps))
+            an = float((gu * du).sum())
+            fd.append({"wrt": "u", "rel_err": abs(num - an) / abs(an)})
+    out = {"p": p, "q": p + 2, "dofs": n, "qpts": op.n_elem * (p + 2) ** 3, "forward_ms": round(fwd_ms, 3),
+           "backward_ms": round(bwd_ms, 3), "kappa_grad_ms": round(kg_ms, 3), "fd_checks": fd}
+    op.close()
+    return out
+
+
+def cg_compare(orders=(3, 5, 7), dofs=3e7):
     import torch
     import synth
     import paper_2109_05072_amd as mf
@@ -215,10 +341,16 @@ def cg_compare(orders=(3,), dofs=3e7):
         r64 = op.cg(b, maxit=20000, rtol=1e-10, mode="f64")
         rmx = op.cg(b, maxit=20000, rtol=1e-10, mode="mixed")
         d = float((rmx.x - r64.x).norm() / r64.x.norm())
-        res.append({"p": p, "dofs": op.n_nodes, "f64_s": r64.seconds, "f64_iters": r64.iters,
-                    "mixed_s": rmx.seconds, "mixed_iters": rmx.iters, "replacements": rmx.replacements,
-                    "speedup": r64.seconds / rmx.seconds, "rel_diff_x": d,
-                    "f64_rel_resid": r64.rel_resid_true, "mixed_rel_resid": rmx.rel_resid_true})
+        ue = torch.from_numpy(synth.sin_solution(op.node_coords().cpu().numpy())).cuda()
+        res.append({"p": p, "dofs": op.n_nodes, "f64_s": round(r64.seconds, 4), "f64_iters": r64.iters,
+                    "mixed_s": round(rmx.seconds, 4), "mixed_iters": rmx.iters, "replacements": rmx.replacements,
+                    "fell_back_to_f64": rmx.fell_back_to_f64, "speedup": round(r64.seconds / rmx.seconds, 3),
+                    "rel_diff_x_mixed_vs_f64": d, "f64_rel_resid": r64.rel_resid_true,
+                    "mixed_rel_resid": rmx.rel_resid_true,
+                    "max_err_vs_exact_f64": float((r64.x - ue).abs().max()),
+                    "max_err_vs_exact_mixed": float((rmx.x - ue).abs().max())})
+        print(f"# cg {res[-1]}", file=sys.stderr, flush=True)
+        op.close()
         del op
         torch.cuda.empty_cache()
     return res

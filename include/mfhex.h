@@ -198,7 +198,7 @@ int mfhex_tune(mfhex_op op, int prec, int nrhs, void *scratch_dev, const char *c
 int mfhex_get_config(mfhex_op op, int prec, int nrhs, int32_t *variant, int32_t *elems_per_group,
                      int32_t *threads_per_group);
 
-/* Force the launch variant (0 .. 4) for (prec, nrhs); MFHEX_ERR_ARG if out of range. */
+/* Force the launch variant (0 .. 8; 5 .. 8 carry 2, 4, 8, 16 vectors of a multi-vector together) for (prec, nrhs); MFHEX_ERR_ARG if out of range. */
 int mfhex_set_config(mfhex_op op, int prec, int nrhs, int32_t variant);
 
 /* Static message for a status code; message of the last failure on a

@@ -124,42 +124,79 @@ __device__ __forceinline__ void contract(const T *src, T *dst, const T *__restri
     }
 }
 
-// Restriction: element values into s0 of each of the G elements.  All loads
-// are issued before any is used (masked nodes read node 0 and are zeroed).
-template <int P, int Q, int G, int NT, int NOFF, typename T>
-__device__ __forceinline__ void gather(T *s0, const int32_t (&off)[NOFF], const T *__restrict__ x, int nvec, int v,
+// Restriction and its transpose work on (node, vector) pairs numbered with
+// the vector fastest: id = (g P^3 + t) VC + vc.  With a chunk of VC vectors,
+// consecutive lanes then touch consecutive doubles of one node's run, so a
+// gather instruction reads whole cache lines and a scatter-add instruction
+// updates whole lines at once instead of hitting the same line VC times.
+template <int P, int G, int NT, int VC>
+struct NodeIO {
+    static constexpr int P3 = P * P * P;
+    static constexpr int NID = G * P3 * VC;
+    static constexpr int NR = (NID + NT - 1) / NT;  // (node, vector) pairs per lane
+};
+
+// off[r] = global node of pair tid + r NT, or -1 (masked, past the group, past nelem).
+template <int P, int G, int NT, int VC, int NR>
+__device__ __forceinline__ void load_offsets(int32_t (&off)[NR], const int32_t *__restrict__ offsets, int64_t e0,
+                                             int64_t nelem, int tid)
+{
+    static_assert(NR == NodeIO<P, G, NT, VC>::NR, "offset count");
+    using IO = NodeIO<P, G, NT, VC>;
+#pragma unroll
+    for (int r = 0; r < IO::NR; ++r) {
+        const int id = tid + r * NT;
+        const int gt = id / VC, g = gt / IO::P3;
+        off[r] = (id < IO::NID && e0 + g < nelem) ? offsets[e0 * IO::P3 + gt] : -1;
+    }
+}
+
+// Element values of vectors v0 .. v0+VC-1 into s0 (virtual element g VC + vc).
+// All loads are issued before any is used; masked nodes read node 0 and
+// vectors past nvec read the last vector, and both are zeroed.
+template <int P, int Q, int G, int NT, int VC, typename T, int NR>
+__device__ __forceinline__ void gather(T *s0, const int32_t (&off)[NR], const T *__restrict__ x, int nvec, int v0,
                                        int tid)
 {
+    static_assert(NR == NodeIO<P, G, NT, VC>::NR, "offset count");
     using L = Lds<Q>;
-    constexpr int P3 = P * P * P;
-    T val[NOFF];
+    using IO = NodeIO<P, G, NT, VC>;
+    T val[IO::NR];
 #pragma unroll
-    for (int r = 0; r < NOFF; ++r) val[r] = x[(int64_t)(off[r] >= 0 ? off[r] : 0) * nvec + v];
+    for (int r = 0; r < IO::NR; ++r) {
+        const int vc = (tid + r * NT) % VC;
+        const int64_t node = off[r] >= 0 ? off[r] : 0;
+        val[r] = x[node * nvec + (v0 + vc < nvec ? v0 + vc : nvec - 1)];
+    }
 #pragma unroll
-    for (int r = 0; r < NOFF; ++r) {
+    for (int r = 0; r < IO::NR; ++r) {
         const int id = tid + r * NT;
-        if (id < G * P3) {
-            const int g = id / P3, t = id - g * P3;
+        if (id < IO::NID) {
+            const int vc = id % VC, gt = id / VC, g = gt / IO::P3, t = gt - g * IO::P3;
             const int i = t % P, j = (t / P) % P, k = t / (P * P);
-            s0[g * L::BUF + i + L::PITCH * j + L::PLANE * k] = off[r] >= 0 ? val[r] : T(0);
+            s0[(g * VC + vc) * L::BUF + i + L::PITCH * j + L::PLANE * k] =
+                (off[r] >= 0 && v0 + vc < nvec) ? val[r] : T(0);
         }
     }
 }
 
-// Transposed restriction: y[node] += s0 for unmasked nodes.
-template <int P, int Q, int G, int NT, int NOFF, typename T>
-__device__ __forceinline__ void scatter_add(const T *s0, const int32_t (&off)[NOFF], T *__restrict__ y, int nvec,
-                                            int v, int tid)
+// Transposed restriction: y[node][v0 + vc] += s0 for unmasked nodes.
+template <int P, int Q, int G, int NT, int VC, typename T, int NR>
+__device__ __forceinline__ void scatter_add(const T *s0, const int32_t (&off)[NR], T *__restrict__ y, int nvec, int v0,
+                                            int tid)
 {
+    static_assert(NR == NodeIO<P, G, NT, VC>::NR, "offset count");
     using L = Lds<Q>;
-    constexpr int P3 = P * P * P;
+    using IO = NodeIO<P, G, NT, VC>;
 #pragma unroll
-    for (int r = 0; r < NOFF; ++r) {
+    for (int r = 0; r < IO::NR; ++r) {
         const int id = tid + r * NT;
-        if (id < G * P3 && off[r] >= 0) {
-            const int g = id / P3, t = id - g * P3;
+        const int vc = id % VC;
+        if (id < IO::NID && off[r] >= 0 && v0 + vc < nvec) {
+            const int gt = id / VC, g = gt / IO::P3, t = gt - g * IO::P3;
             const int i = t % P, j = (t / P) % P, k = t / (P * P);
-            unsafeAtomicAdd(&y[(int64_t)off[r] * nvec + v], s0[g * L::BUF + i + L::PITCH * j + L::PLANE * k]);
+            unsafeAtomicAdd(&y[(int64_t)off[r] * nvec + v0 + vc],
+                            s0[(g * VC + vc) * L::BUF + i + L::PITCH * j + L::PLANE * k]);
         }
     }
 }
@@ -192,34 +229,54 @@ __device__ __forceinline__ void grad(T *s0, T *s1, T *s2, const T *__restrict__ 
 
 // ---------------------------------------------------------------------------
 // y += A x  (mass / diffusion), or y += B^T (w detJ f) for the load vector.
+// VC vectors of the multi-vector travel together (virtual elements g*VC + vc).
 // ---------------------------------------------------------------------------
-template <int P, int Q, bool COLLOC, int MODE, bool VARK, typename T, int G, int NT>
+template <int P, int Q, bool COLLOC, int MODE, bool VARK, typename T, int G, int NT, int VC>
 __global__ void __launch_bounds__(NT)
 k_apply(const T *__restrict__ bas, const int64_t nelem, const int nvec, const int32_t *__restrict__ offsets,
         const T *__restrict__ qdata, const double *__restrict__ kappa, const double *__restrict__ wdet,
         const T *__restrict__ x, T *__restrict__ y)
 {
-    constexpr int Q2 = Q * Q, Q3 = Q2 * Q, P3 = P * P * P;
-    constexpr int NOFF = (G * P3 + NT - 1) / NT;
+    constexpr int Q2 = Q * Q, Q3 = Q2 * Q;
     constexpr int NPT = G * Q3, RQ = (NPT + NT - 1) / NT;
+    constexpr int GV = G * VC;
     using L = Lds<Q>;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T *const s0 = reinterpret_cast<T *>(smem_raw);
-    T *const s1 = s0 + G * L::BUF;
-    T *const s2 = s1 + G * L::BUF;
+    T *const s1 = s0 + GV * L::BUF;
+    T *const s2 = s1 + GV * L::BUF;
     const int tid = threadIdx.x;
     const int64_t e0 = xcd_block(blockIdx.x, gridDim.x) * G;
 
-    int32_t off[NOFF];
+    int32_t off[NodeIO<P, G, NT, VC>::NR];
+    load_offsets<P, G, NT, VC>(off, offsets, e0, nelem, tid);
+
+    // This lane's geometric factors, loaded once per element group and issued
+    // first, so their HBM latency overlaps the gather and the forward
+    // contractions, and every chunk of vectors reuses them.
+    constexpr int NQD = MODE == kMass ? 1 : MODE == kDiff ? kQdDiff : 0;
+    T qv[RQ][NQD > 0 ? NQD : 1];
+    if constexpr (NQD > 0) {
 #pragma unroll
-    for (int r = 0; r < NOFF; ++r) {
-        const int id = tid + r * NT;
-        const int g = id / P3;
-        off[r] = (id < G * P3 && e0 + g < nelem) ? offsets[e0 * P3 + id] : -1;
+        for (int k = 0; k < RQ; ++k) {
+            const int id = tid + k * NT < NPT ? tid + k * NT : NPT - 1;
+            const int g = id / Q3, pt = id - g * Q3;
+            // the tail group reads the last element's data (and scatters nothing)
+            const int64_t e = e0 + g < nelem ? e0 + g : nelem - 1;
+            const T *qd = qdata + e * (NQD * Q3) + pt;
+#pragma unroll
+            for (int m = 0; m < NQD; ++m) qv[k][m] = __builtin_nontemporal_load(&qd[m * Q3]);
+            if constexpr (VARK) {
+                const T kap = T(kappa[e * Q3 + pt]);
+#pragma unroll
+                for (int m = 0; m < NQD; ++m) qv[k][m] *= kap;
+            }
+        }
     }
 
-    for (int v = 0; v < nvec; ++v) {
+    for (int v0 = 0; v0 < nvec; v0 += VC) {
         if constexpr (MODE == kRhs) {
+            static_assert(VC == 1, "load vector: one vector");
             const double *f = reinterpret_cast<const double *>(x);
 #pragma unroll 4
             for (int k = 0; k < RQ; ++k) {
@@ -233,68 +290,62 @@ k_apply(const T *__restrict__ bas, const int64_t nelem, const int nvec, const in
             }
             group_sync<NT>();
         } else {
-            gather<P, Q, G, NT, NOFF, T>(s0, off, x, nvec, v, tid);
+            gather<P, Q, G, NT, VC, T>(s0, off, x, nvec, v0, tid);
             group_sync<NT>();
-            interp<P, Q, COLLOC, G, NT, T>(s0, bas, tid);
+            interp<P, Q, COLLOC, GV, NT, T>(s0, bas, tid);
             if constexpr (MODE == kMass) {
-#pragma unroll 4
+#pragma unroll
                 for (int k = 0; k < RQ; ++k) {
                     const int id = tid + k * NT;
                     if (id < NPT) {
                         const int g = id / Q3, pt = id - g * Q3;
                         const int a = pt % Q, b = (pt / Q) % Q, c = pt / Q2;
-                        const int ls = g * L::BUF + a + L::PITCH * b + L::PLANE * c;
-                        const int64_t e = e0 + g < nelem ? e0 + g : nelem - 1;
-                        s0[ls] *= __builtin_nontemporal_load(&qdata[e * Q3 + pt]);
+                        const int loc = a + L::PITCH * b + L::PLANE * c;
+#pragma unroll
+                        for (int vc = 0; vc < VC; ++vc) s0[(g * VC + vc) * L::BUF + loc] *= qv[k][0];
                     }
                 }
                 group_sync<NT>();
             } else {
-                grad<P, Q, G, NT, T>(s0, s1, s2, bas, tid);
-#pragma unroll 4
+                grad<P, Q, GV, NT, T>(s0, s1, s2, bas, tid);
+#pragma unroll
                 for (int k = 0; k < RQ; ++k) {
                     const int id = tid + k * NT;
                     if (id < NPT) {
                         const int g = id / Q3, pt = id - g * Q3;
                         const int a = pt % Q, b = (pt / Q) % Q, c = pt / Q2;
-                        const int ls = g * L::BUF + a + L::PITCH * b + L::PLANE * c;
-                        // the tail group reads the last element's data (and scatters nothing)
-                        const int64_t e = e0 + g < nelem ? e0 + g : nelem - 1;
-                        const T *qd = qdata + e * (kQdDiff * Q3) + pt;
-                        T gm[kQdDiff];
+                        const int loc = a + L::PITCH * b + L::PLANE * c;
+                        const T *gm = qv[k];
 #pragma unroll
-                        for (int m = 0; m < kQdDiff; ++m) gm[m] = __builtin_nontemporal_load(&qd[m * Q3]);
-                        if constexpr (VARK) {
-                            const T kap = T(kappa[e * Q3 + pt]);
-#pragma unroll
-                            for (int m = 0; m < kQdDiff; ++m) gm[m] *= kap;
+                        for (int vc = 0; vc < VC; ++vc) {
+                            const int ls = (g * VC + vc) * L::BUF + loc;
+                            const T ur = s1[ls], us = s2[ls], ut = s0[ls];
+                            s1[ls] = gm[0] * ur + gm[5] * us + gm[4] * ut;
+                            s2[ls] = gm[5] * ur + gm[1] * us + gm[3] * ut;
+                            s0[ls] = gm[4] * ur + gm[3] * us + gm[2] * ut;
                         }
-                        const T ur = s1[ls], us = s2[ls], ut = s0[ls];
-                        s1[ls] = gm[0] * ur + gm[5] * us + gm[4] * ut;
-                        s2[ls] = gm[5] * ur + gm[1] * us + gm[3] * ut;
-                        s0[ls] = gm[4] * ur + gm[3] * us + gm[2] * ut;
                     }
                 }
                 group_sync<NT>();
                 // transposed gradient: x and y lines in place, then the z lines
                 // of s0 with the x and y parts added
-                contract<0, Q, Q, Q, Q, G, NT, Q>(s1, s1, bas + basis_dt(P, Q), tid);
-                contract<1, Q, Q, Q, Q, G, NT, Q>(s2, s2, bas + basis_dt(P, Q), tid);
+                contract<0, Q, Q, Q, Q, GV, NT, Q>(s1, s1, bas + basis_dt(P, Q), tid);
+                contract<1, Q, Q, Q, Q, GV, NT, Q>(s2, s2, bas + basis_dt(P, Q), tid);
                 group_sync<NT>();
-                contract<2, Q, Q, Q, Q, G, NT, Q, T, true>(s0, s0, bas + basis_dt(P, Q), tid, s1, s2);
+                contract<2, Q, Q, Q, Q, GV, NT, Q, T, true>(s0, s0, bas + basis_dt(P, Q), tid, s1, s2);
                 // same lines, same lanes: B^T along z follows without a sync
             }
         }
         // transposed interpolation back to the nodes
         if constexpr (!COLLOC) {
-            contract<2, Q, Q, Q, P, G, NT, Q>(s0, s0, bas + basis_bt(P, Q), tid);
+            contract<2, Q, Q, Q, P, GV, NT, Q>(s0, s0, bas + basis_bt(P, Q), tid);
             group_sync<NT>();
-            contract<1, Q, Q, P, P, G, NT, Q>(s0, s0, bas + basis_bt(P, Q), tid);
+            contract<1, Q, Q, P, P, GV, NT, Q>(s0, s0, bas + basis_bt(P, Q), tid);
             group_sync<NT>();
-            contract<0, Q, P, P, P, G, NT, Q>(s0, s0, bas + basis_bt(P, Q), tid);
+            contract<0, Q, P, P, P, GV, NT, Q>(s0, s0, bas + basis_bt(P, Q), tid);
         }
         group_sync<NT>();
-        scatter_add<P, Q, G, NT, NOFF, T>(s0, off, y, nvec, v, tid);
+        scatter_add<P, Q, G, NT, VC, T>(s0, off, y, nvec, v0, tid);
         group_sync<NT>();
     }
 }
@@ -309,8 +360,7 @@ k_kgrad(const double *__restrict__ bas, const int64_t nelem, const int32_t *__re
         double *__restrict__ gout)
 {
     using T = double;
-    constexpr int Q2 = Q * Q, Q3 = Q2 * Q, P3 = P * P * P;
-    constexpr int NOFF = (G * P3 + NT - 1) / NT;
+    constexpr int Q2 = Q * Q, Q3 = Q2 * Q;
     constexpr int NPT = G * Q3, RQ = (NPT + NT - 1) / NT;
     using L = Lds<Q>;
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -322,15 +372,10 @@ k_kgrad(const double *__restrict__ bas, const int64_t nelem, const int32_t *__re
     T *const t2 = t1 + G * L::BUF;
     const int tid = threadIdx.x;
     const int64_t e0 = xcd_block(blockIdx.x, gridDim.x) * G;
-    int32_t off[NOFF];
-#pragma unroll
-    for (int rr = 0; rr < NOFF; ++rr) {
-        const int id = tid + rr * NT;
-        const int g = id / P3;
-        off[rr] = (id < G * P3 && e0 + g < nelem) ? offsets[e0 * P3 + id] : -1;
-    }
-    gather<P, Q, G, NT, NOFF, T>(s0, off, u, 1, 0, tid);
-    gather<P, Q, G, NT, NOFF, T>(t0, off, r, 1, 0, tid);
+    int32_t off[NodeIO<P, G, NT, 1>::NR];
+    load_offsets<P, G, NT, 1>(off, offsets, e0, nelem, tid);
+    gather<P, Q, G, NT, 1, T>(s0, off, u, 1, 0, tid);
+    gather<P, Q, G, NT, 1, T>(t0, off, r, 1, 0, tid);
     group_sync<NT>();
     interp<P, Q, COLLOC, G, NT, T>(s0, bas, tid);
     interp<P, Q, COLLOC, G, NT, T>(t0, bas, tid);
@@ -369,29 +414,38 @@ static hipError_t prepare_lds(K kernel, size_t lds)
     return hipSuccess;
 }
 
-template <int P, int Q, bool COLLOC, int MODE, bool VARK, typename T, int G, int NT>
+template <int P, int Q, bool COLLOC, int MODE, bool VARK, typename T, int V>
 static hipError_t launch_apply_v(const ApplyLaunch &a)
 {
-    const int64_t nblk = (a.v.nelem + G - 1) / G;
-    const size_t lds = (size_t)G * apply_nbuf(MODE) * Lds<Q>::BUF * sizeof(T);
-    auto kern = k_apply<P, Q, COLLOC, MODE, VARK, T, G, NT>;
-    hipError_t err = prepare_lds(kern, lds);
-    if (err != hipSuccess) return err;
-    hipLaunchKernelGGL(kern, dim3((unsigned)nblk), dim3(NT), lds, a.stream, static_cast<const T *>(a.basis_dev),
-                       a.v.nelem, a.nvec, a.v.offsets, static_cast<const T *>(a.v.qdata), a.v.kappa, a.wdet,
-                       static_cast<const T *>(a.x), static_cast<T *>(a.y));
-    return hipGetLastError();
+    constexpr int G = variant_g(Q, V, MODE), NT = variant_nt(Q, V), VC = variant_vc(V);
+    constexpr size_t lds = apply_lds(Q, MODE, sizeof(T), V);
+    // chunked multi-vector variants exist for the plain mass / diffusion operators only
+    if constexpr ((VC > 1 && (MODE == kRhs || VARK)) || lds > kMaxLds) {
+        (void)a;
+        return hipErrorInvalidValue;
+    } else {
+        const int64_t nblk = (a.v.nelem + G - 1) / G;
+        auto kern = k_apply<P, Q, COLLOC, MODE, VARK, T, G, NT, VC>;
+        hipLaunchKernelGGL(kern, dim3((unsigned)nblk), dim3(NT), lds, a.stream, static_cast<const T *>(a.basis_dev),
+                           a.v.nelem, a.nvec, a.v.offsets, static_cast<const T *>(a.v.qdata), a.v.kappa, a.wdet,
+                           static_cast<const T *>(a.x), static_cast<T *>(a.y));
+        return hipGetLastError();
+    }
 }
 
 template <int P, int Q, bool COLLOC, int MODE, bool VARK, typename T>
 static hipError_t launch_apply_t(const ApplyLaunch &a)
 {
     switch (a.variant) {
-    case 0: return launch_apply_v<P, Q, COLLOC, MODE, VARK, T, variant_g(Q, 0), variant_nt(Q, 0)>(a);
-    case 1: return launch_apply_v<P, Q, COLLOC, MODE, VARK, T, variant_g(Q, 1), variant_nt(Q, 1)>(a);
-    case 2: return launch_apply_v<P, Q, COLLOC, MODE, VARK, T, variant_g(Q, 2), variant_nt(Q, 2)>(a);
-    case 3: return launch_apply_v<P, Q, COLLOC, MODE, VARK, T, variant_g(Q, 3), variant_nt(Q, 3)>(a);
-    case 4: return launch_apply_v<P, Q, COLLOC, MODE, VARK, T, variant_g(Q, 4), variant_nt(Q, 4)>(a);
+    case 8: return launch_apply_v<P, Q, COLLOC, MODE, VARK, T, 8>(a);
+    case 0: return launch_apply_v<P, Q, COLLOC, MODE, VARK, T, 0>(a);
+    case 1: return launch_apply_v<P, Q, COLLOC, MODE, VARK, T, 1>(a);
+    case 2: return launch_apply_v<P, Q, COLLOC, MODE, VARK, T, 2>(a);
+    case 3: return launch_apply_v<P, Q, COLLOC, MODE, VARK, T, 3>(a);
+    case 4: return launch_apply_v<P, Q, COLLOC, MODE, VARK, T, 4>(a);
+    case 5: return launch_apply_v<P, Q, COLLOC, MODE, VARK, T, 5>(a);
+    case 6: return launch_apply_v<P, Q, COLLOC, MODE, VARK, T, 6>(a);
+    case 7: return launch_apply_v<P, Q, COLLOC, MODE, VARK, T, 7>(a);
     default: return hipErrorInvalidValue;
     }
 }

@@ -130,15 +130,18 @@ int mode_of(const mfhex_op_s &op) { return op.d.kind == MFHEX_DIFFUSION ? kDiff 
 
 bool valid_variant(const mfhex_op_s &op, int prec, int variant)
 {
-    (void)op;
-    return (prec == MFHEX_F64 || prec == MFHEX_F32) && variant >= 0 && variant < kNumVariants;
+    if ((prec != MFHEX_F64 && prec != MFHEX_F32) || variant < 0 || variant >= kNumVariants) return false;
+    if (variant_vc(variant) > 1 && op.d.variable_kappa) return false;
+    return apply_lds(op.Q, mode_of(op), prec == MFHEX_F32 ? 4 : 8, variant) <= kMaxLds;
 }
 
 int default_variant(const mfhex_op_s &op, int prec, int nvec)
 {
-    (void)op;
-    (void)prec;
-    (void)nvec;
+    // one vector: the measured single-vector best; several: the largest chunk that
+    // fits the LDS budget and does not exceed the vector count
+    if (nvec <= 1) return 0;
+    for (int v = kNumVariants - 1; v >= 5; --v)
+        if (variant_vc(v) <= nvec && valid_variant(op, prec, v)) return v;
     return 0;
 }
 
@@ -459,7 +462,7 @@ int mfhex_get_config(mfhex_op op, int prec, int nrhs, int32_t *variant, int32_t 
     if (!op || nrhs < 1) return fail(MFHEX_ERR_ARG, "bad argument");
     const int v = variant_for(*op, prec, nrhs * op->d.ncomp);
     if (variant) *variant = v;
-    if (elems_per_group) *elems_per_group = variant_g(op->Q, v);
+    if (elems_per_group) *elems_per_group = variant_g(op->Q, v, mode_of(*op));
     if (threads_per_group) *threads_per_group = variant_nt(op->Q, v);
     return MFHEX_OK;
 }

@@ -4,7 +4,10 @@
 // sum-factorized operator evaluation; the benchmarks of Sec. 2 run it
 // unpreconditioned).  One iteration is apply, dot, fused x/r update with the
 // new residual norm, and the direction update; alpha and beta never leave the
-// GPU.  The host reads the scalars back every `check_every` iterations.
+// GPU.  The host reads the scalars back every `check_every` iterations.  When
+// the recursive residual reaches the tolerance, the true residual b - A x is
+// computed; the solve stops only if it meets the tolerance too, and otherwise
+// continues from it.
 //
 // Mixed mode (reliable updates): the operator, r, p and Ap are FP32 (FP32
 // geometric factors and accumulation), x stays FP64 and every dot product
@@ -97,8 +100,23 @@ int cg64(Ctx &ctx, const double *b, double *x, const mfhex_cg_opts &o, bool x0_z
                 break;
             }
             if (std::sqrt(h[kScRRNew]) <= o.rtol * bnorm) {
-                status = MFHEX_OK;
-                break;
+                // the recursive residual claims convergence: accept only on the true residual,
+                // otherwise continue from the true residual (beta from it, direction kept)
+                const double rr_old = h[kScRRPrev];
+                TRY(true_residual(ctx, b, x, ctx.r64, nullptr));
+                TRY(read_scalars(ctx));
+                double *hp = ctx.op->pinned;
+                if (std::sqrt(hp[kScRRTrue]) <= o.rtol * bnorm) {
+                    status = MFHEX_OK;
+                    break;
+                }
+                hp[kScRR] = hp[kScRRTrue];
+                hp[kScBeta] = hp[kScRRTrue] / rr_old;
+                HIP(hipMemcpyAsync(ctx.sc + kScRR, hp + kScRR, sizeof(double), hipMemcpyHostToDevice, ctx.s),
+                    "write scalar");
+                HIP(hipMemcpyAsync(ctx.sc + kScBeta, hp + kScBeta, sizeof(double), hipMemcpyHostToDevice, ctx.s),
+                    "write scalar");
+                HIP(hipStreamSynchronize(ctx.s), "hipStreamSynchronize");
             }
         }
         HIP(launch_update_p(ctx.r64, ctx.p64, MFHEX_F64, ctx.sc, n, ctx.s), "update kernel");

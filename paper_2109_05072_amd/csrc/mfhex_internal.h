@@ -77,17 +77,38 @@ constexpr int apply_nbuf(int mode) { return mode == 1 ? 3 : 1; }
 
 // Launch variants of the fused kernels for q points per direction: G
 // elements per thread group of NT threads; variant 0 is the default.
-constexpr int kNumVariants = 5;
-// rows: Q = 2 .. 10; variant 0 is the measured best on MI355X (BP3 FP64, 1e7 nodes)
-constexpr int kVarG[9][kNumVariants] = {
-    {16, 8, 32, 16, 32}, {8, 4, 16, 8, 16}, {4, 2, 8, 4, 8}, {4, 2, 1, 2, 4}, {2, 2, 1, 4, 1},
-    {1, 1, 2, 2, 1},     {1, 1, 2, 2, 1},   {1, 1, 2, 1, 2}, {1, 1, 2, 1, 2}};
-constexpr int kVarNT[9][kNumVariants] = {
+// Variants 0..4 carry one vector at a time through the element (rows: Q = 2
+// .. 10; variant 0 is the measured best on MI355X for one vector); variants
+// 5..8 carry a chunk of VC = 2, 4, 8, 16 vectors of a multi-vector together
+// (one element per group), sharing the geometric factors and reading /
+// writing each node's chunk as one contiguous run.
+constexpr int kNumVariants = 9;
+constexpr int kVarG[9][5] = {
+    {16, 8, 32, 16, 32}, {8, 4, 16, 8, 16}, {4, 2, 8, 4, 8}, {2, 2, 1, 4, 4}, {1, 2, 1, 2, 4},
+    {2, 1, 1, 1, 2},     {1, 1, 1, 2, 2},   {1, 1, 1, 2, 2}, {1, 1, 1, 2, 2}};
+constexpr int kVarNT[9][5] = {
     {64, 64, 64, 128, 128},  {64, 64, 64, 128, 128},  {64, 64, 64, 128, 128},
-    {128, 64, 64, 128, 64},  {128, 64, 64, 128, 128}, {128, 64, 64, 128, 256},
-    {128, 64, 64, 128, 256}, {128, 64, 128, 256, 256}, {128, 64, 128, 256, 256}};
-constexpr int variant_g(int Q, int v) { return kVarG[Q - 2][v]; }
-constexpr int variant_nt(int Q, int v) { return kVarNT[Q - 2][v]; }
+    {128, 64, 64, 128, 64},  {128, 64, 64, 128, 128}, {128, 64, 128, 256, 64},
+    {256, 128, 64, 128, 64}, {256, 128, 64, 128, 256}, {256, 128, 64, 128, 256}};
+constexpr int variant_vc(int v) { return v < 5 ? 1 : v == 5 ? 2 : v == 6 ? 4 : v == 7 ? 8 : 16; }
+// The mass operator keeps one LDS array per element instead of three and has
+// far less work per element, so at low order its single-vector variants
+// carry more elements per group.
+constexpr int mass_group_scale(int Q) { return Q <= 4 ? 4 : Q <= 6 ? 2 : 1; }
+constexpr int variant_g(int Q, int v, int mode = 1)
+{
+    return v < 5 ? kVarG[Q - 2][v] * (mode == 1 ? 1 : mass_group_scale(Q)) : 1;
+}
+constexpr int variant_nt(int Q, int v)
+{
+    return v < 5 ? kVarNT[Q - 2][v] : (Q * Q * variant_vc(v) <= 64 ? 64 : Q * Q * variant_vc(v) <= 128 ? 128 : 256);
+}
+// Dynamic LDS bytes of one group of the fused apply.
+constexpr size_t apply_lds(int Q, int mode, int elem_bytes, int v)
+{
+    return (size_t)variant_g(Q, v, mode) * variant_vc(v) * apply_nbuf(mode) * lds_buf(Q) * elem_bytes;
+}
+constexpr size_t kMaxLds = 65536;
 // Size of the device basis block in elements: B, B^T (q x p+1 each), D, D^T (q x q each).
 constexpr int basis_len(int P, int Q) { return 2 * Q * P + 2 * Q * Q; }
 

@@ -56,15 +56,17 @@ def host(t):
     return t.double().cpu().numpy()
 
 
-def ragged_variant(op, dtype=torch.float64):
-    """A launch variant whose group size does not divide the element count."""
-    for v in range(5):
-        op.set_config(v, dtype)
-        g = op.get_config(dtype)[1]
-        if op.n_elem % g and op.n_elem > g:
-            return v
-    op.set_config(0, dtype)
-    return None
+def valid_variants(op, dtype=torch.float64, nrhs=1):
+    """Launch variants the operator accepts (some exceed the LDS budget at high order)."""
+    from paper_2109_05072_amd import _lib as L
+    out = []
+    for v in range(9):
+        try:
+            op.set_config(v, dtype, nrhs)
+            out.append(v)
+        except L.MFHexError:
+            pass
+    return out
 
 
 # --- apply parity across orders, rules, masks ------------------------------------------------
@@ -79,7 +81,7 @@ def test_apply_fp64_matches_oracle(gpu_lib, p, kind, quad, dirichlet):
     yo = oracle.apply(pr, x)
     y = host(op.apply(dev(x)))
     assert relerr(y, yo) <= TOL64
-    for v in range(5):
+    for v in valid_variants(op):
         op.set_config(v)
         _say("apply64 variant", v, op.get_config())
         y2 = host(op.apply(dev(x)))
@@ -107,6 +109,11 @@ def test_multivector_matches_oracle_and_looped(gpu_lib, p, ncomp, nrhs, quad):
     yo = oracle.apply(pr, x)
     y = host(op.apply(dev(x)))
     assert relerr(y, yo) <= TOL64
+    # every launch variant, including chunks of 2/4/8 vectors that do not divide nvec
+    for v in valid_variants(op, nrhs=nrhs):
+        op.set_config(v, nrhs=nrhs)
+        _say("multivector variant", v, op.get_config(nrhs=nrhs))
+        assert relerr(host(op.apply(dev(x))), yo) <= TOL64
     # one launch for all vectors == separate single-vector launches
     if ncomp == 1:
         single, _ = build(gpu_lib, 3, 3, 2, p, "diffusion", quad, True)
@@ -188,13 +195,15 @@ def test_every_launch_configuration_agrees(gpu_lib, p, quad, nrhs):
     op, pr = build(gpu_lib, 4, 3, 3, p, "diffusion", quad)
     x = dev(synth.uniform_vector(pr.n_nodes, nvec=nrhs))
     ref = host(op.apply(x))
-    for v in range(5):
+    vs = valid_variants(op, nrhs=nrhs)
+    assert 0 in vs
+    for v in vs:
         op.set_config(v, nrhs=nrhs)
         assert relerr(host(op.apply(x)), ref) <= 1e-13
     with pytest.raises(L.MFHexError):
-        op.set_config(5, nrhs=nrhs)
+        op.set_config(9, nrhs=nrhs)
     best = op.tune(nrhs=nrhs)
-    assert best[0] in range(5)
+    assert best[0] in vs
     assert relerr(host(op.apply(x)), ref) <= 1e-13
 
 
