@@ -43,13 +43,6 @@ struct Lds {
     static constexpr int BUF = lds_buf(Q);
 };
 
-// Offsets of the matrices in the device basis block: B [Q][P], Bt [P][Q],
-// D [Q][Q], Dt [Q][Q], all row-major.
-constexpr int basis_b(int, int) { return 0; }
-constexpr int basis_bt(int P, int Q) { return Q * P; }
-constexpr int basis_d(int P, int Q) { return 2 * Q * P; }
-constexpr int basis_dt(int P, int Q) { return 2 * Q * P + Q * Q; }
-
 // Blocks are dealt to the 8 XCDs round-robin; renumber them so that each XCD
 // works on one contiguous range of elements (neighbouring elements share
 // nodes, so their gathers and scatter-adds stay in that XCD's L2).
@@ -76,12 +69,21 @@ __device__ __forceinline__ void group_sync()
 }
 
 // Contract axis AX of the G element arrays (extents E0 x E1 x E2 before the
-// contraction) from NI = E_AX to NO entries with M (row-major NO x NI):
-// dst[..o..] = sum_i M[o][i] src[..i..] (+ a1[..o..] + a2[..o..] with ADD2).
-// Every lane handles the same lines for a given (AX, extents), so a second
-// contraction along the same axis may follow without a sync.
-template <int AX, int E0, int E1, int E2, int NO, int G, int NT, int Q, typename T, bool ADD2 = false>
-__device__ __forceinline__ void contract(const T *src, T *dst, const T *__restrict__ M, int tid, const T *a1 = nullptr,
+// contraction) from NI = E_AX to NO entries: dst[..o..] = sum_i M[o][i]
+// src[..i..] (+ a1[..o..] + a2[..o..] with ADD2).  Every lane handles the same
+// lines for a given (AX, extents), so a second contraction along the same axis
+// may follow without a sync.
+//
+// The 1D matrices are centro-symmetric (B, B^T: M[NO-1-o][NI-1-i] = M[o][i],
+// SYM = +1) or anti-centro-symmetric (D, D^T: = -M[o][i], SYM = -1), because
+// nodes and points are symmetric about 0.  The contraction is evaluated in
+// even-odd form: with e_i = v_i + v_{NI-1-i} and d_i = v_i - v_{NI-1-i},
+//   E_o = sum_i Me[o][i] e_i (+ M[o][mid] v_mid),  O_o = sum_i Mo[o][i] d_i,
+//   out_o = E_o + O_o,   out_{NO-1-o} = SYM (E_o - O_o),   o < ceil(NO/2),
+// which halves the multiply-adds; MF points at the folded rows
+// [Me[o][0..NI/2) | Mo[o][0..NI/2) | M[o][mid]].
+template <int AX, int E0, int E1, int E2, int NO, int G, int NT, int Q, int SYM, typename T, bool ADD2 = false>
+__device__ __forceinline__ void contract(const T *src, T *dst, const T *__restrict__ MF, int tid, const T *a1 = nullptr,
                                          const T *a2 = nullptr)
 {
     using L = Lds<Q>;
@@ -93,7 +95,8 @@ __device__ __forceinline__ void contract(const T *src, T *dst, const T *__restri
     constexpr int ST = AX == 0 ? 1 : AX == 1 ? L::PITCH : L::PLANE;  // stride along the line
     constexpr int NPEN = G * NA * NB;
     constexpr int R = (NPEN + NT - 1) / NT;
-    T v[R][NI];
+    constexpr int H = NI / 2, MID = NI & 1, NOH = (NO + 1) / 2;
+    T ev[R][H + MID], dv[R][H > 0 ? H : 1];
     int base[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
@@ -102,23 +105,41 @@ __device__ __forceinline__ void contract(const T *src, T *dst, const T *__restri
         if (id < NPEN) {
             const int a = id % NA, t = id / NA, b = t % NB, g = t / NB;
             base[r] = g * L::BUF + a * SA + b * SB;
+            T v[NI];
 #pragma unroll
-            for (int i = 0; i < NI; ++i) v[r][i] = src[base[r] + i * ST];
+            for (int i = 0; i < NI; ++i) v[i] = src[base[r] + i * ST];
+#pragma unroll
+            for (int i = 0; i < H; ++i) {
+                ev[r][i] = v[i] + v[NI - 1 - i];
+                dv[r][i] = v[i] - v[NI - 1 - i];
+            }
+            if constexpr (MID) ev[r][H] = v[H];
         }
     }
-    // coefficient rows in flight per scalar-load wait: at least two, about 24 coefficients
+    // coefficient half-rows in flight per scalar-load wait: about 24 coefficients
     constexpr int UR = NI >= 12 ? 2 : 24 / NI;
 #pragma unroll UR
-    for (int o = 0; o < NO; ++o) {
-        const T *row = M + o * NI;
+    for (int o = 0; o < NOH; ++o) {
+        const T *row = MF + o * NI;
+        const int om = NO - 1 - o;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             if (base[r] >= 0) {
-                T acc = T(0);
+                T E = T(0), O = T(0);
 #pragma unroll
-                for (int i = 0; i < NI; ++i) acc += row[i] * v[r][i];
-                if constexpr (ADD2) acc += a1[base[r] + o * ST] + a2[base[r] + o * ST];
-                dst[base[r] + o * ST] = acc;
+                for (int i = 0; i < H; ++i) {
+                    E += row[i] * ev[r][i];
+                    O += row[H + i] * dv[r][i];
+                }
+                if constexpr (MID) E += row[2 * H] * ev[r][H];
+                T lo = E + O;
+                T hi = SYM > 0 ? E - O : O - E;
+                if constexpr (ADD2) {
+                    lo += a1[base[r] + o * ST] + a2[base[r] + o * ST];
+                    hi += a1[base[r] + om * ST] + a2[base[r] + om * ST];
+                }
+                dst[base[r] + o * ST] = lo;
+                if (om != o) dst[base[r] + om * ST] = hi;
             }
         }
     }
@@ -206,11 +227,11 @@ template <int P, int Q, bool COLLOC, int G, int NT, typename T>
 __device__ __forceinline__ void interp(T *s0, const T *__restrict__ bas, int tid)
 {
     if constexpr (!COLLOC) {
-        contract<0, P, P, P, Q, G, NT, Q>(s0, s0, bas + basis_b(P, Q), tid);
+        contract<0, P, P, P, Q, G, NT, Q, 1>(s0, s0, bas + basis_bf(P, Q), tid);
         group_sync<NT>();
-        contract<1, Q, P, P, Q, G, NT, Q>(s0, s0, bas + basis_b(P, Q), tid);
+        contract<1, Q, P, P, Q, G, NT, Q, 1>(s0, s0, bas + basis_bf(P, Q), tid);
         group_sync<NT>();
-        contract<2, Q, Q, P, Q, G, NT, Q>(s0, s0, bas + basis_b(P, Q), tid);
+        contract<2, Q, Q, P, Q, G, NT, Q, 1>(s0, s0, bas + basis_bf(P, Q), tid);
         group_sync<NT>();
     }
 }
@@ -220,10 +241,10 @@ __device__ __forceinline__ void interp(T *s0, const T *__restrict__ bas, int tid
 template <int P, int Q, int G, int NT, typename T>
 __device__ __forceinline__ void grad(T *s0, T *s1, T *s2, const T *__restrict__ bas, int tid)
 {
-    contract<0, Q, Q, Q, Q, G, NT, Q>(s0, s1, bas + basis_d(P, Q), tid);
-    contract<1, Q, Q, Q, Q, G, NT, Q>(s0, s2, bas + basis_d(P, Q), tid);
+    contract<0, Q, Q, Q, Q, G, NT, Q, -1>(s0, s1, bas + basis_df(P, Q), tid);
+    contract<1, Q, Q, Q, Q, G, NT, Q, -1>(s0, s2, bas + basis_df(P, Q), tid);
     group_sync<NT>();
-    contract<2, Q, Q, Q, Q, G, NT, Q>(s0, s0, bas + basis_d(P, Q), tid);
+    contract<2, Q, Q, Q, Q, G, NT, Q, -1>(s0, s0, bas + basis_df(P, Q), tid);
     group_sync<NT>();
 }
 
@@ -329,20 +350,20 @@ k_apply(const T *__restrict__ bas, const int64_t nelem, const int nvec, const in
                 group_sync<NT>();
                 // transposed gradient: x and y lines in place, then the z lines
                 // of s0 with the x and y parts added
-                contract<0, Q, Q, Q, Q, GV, NT, Q>(s1, s1, bas + basis_dt(P, Q), tid);
-                contract<1, Q, Q, Q, Q, GV, NT, Q>(s2, s2, bas + basis_dt(P, Q), tid);
+                contract<0, Q, Q, Q, Q, GV, NT, Q, -1>(s1, s1, bas + basis_dtf(P, Q), tid);
+                contract<1, Q, Q, Q, Q, GV, NT, Q, -1>(s2, s2, bas + basis_dtf(P, Q), tid);
                 group_sync<NT>();
-                contract<2, Q, Q, Q, Q, GV, NT, Q, T, true>(s0, s0, bas + basis_dt(P, Q), tid, s1, s2);
+                contract<2, Q, Q, Q, Q, GV, NT, Q, -1, T, true>(s0, s0, bas + basis_dtf(P, Q), tid, s1, s2);
                 // same lines, same lanes: B^T along z follows without a sync
             }
         }
         // transposed interpolation back to the nodes
         if constexpr (!COLLOC) {
-            contract<2, Q, Q, Q, P, GV, NT, Q>(s0, s0, bas + basis_bt(P, Q), tid);
+            contract<2, Q, Q, Q, P, GV, NT, Q, 1>(s0, s0, bas + basis_btf(P, Q), tid);
             group_sync<NT>();
-            contract<1, Q, Q, P, P, GV, NT, Q>(s0, s0, bas + basis_bt(P, Q), tid);
+            contract<1, Q, Q, P, P, GV, NT, Q, 1>(s0, s0, bas + basis_btf(P, Q), tid);
             group_sync<NT>();
-            contract<0, Q, P, P, P, GV, NT, Q>(s0, s0, bas + basis_bt(P, Q), tid);
+            contract<0, Q, P, P, P, GV, NT, Q, 1>(s0, s0, bas + basis_btf(P, Q), tid);
         }
         group_sync<NT>();
         scatter_add<P, Q, G, NT, VC, T>(s0, off, y, nvec, v0, tid);

@@ -319,6 +319,21 @@ int mfhex_create(const mfhex_desc *d, void *workspace_dev, size_t workspace_byte
                 h[2 * Q * P + a * Q + k] = b.D[a * Q + k];
                 h[2 * Q * P + Q * Q + k * Q + a] = b.D[a * Q + k];
             }
+        // folded (even-odd) rows of a NO x NI row-major matrix at `m` into `f`
+        auto fold = [](const double *m, int NO, int NI, double *f) {
+            const int H = NI / 2;
+            for (int o = 0; o < (NO + 1) / 2; ++o) {
+                for (int i = 0; i < H; ++i) {
+                    f[o * NI + i] = 0.5 * (m[o * NI + i] + m[o * NI + NI - 1 - i]);
+                    f[o * NI + H + i] = 0.5 * (m[o * NI + i] - m[o * NI + NI - 1 - i]);
+                }
+                if (NI & 1) f[o * NI + 2 * H] = m[o * NI + H];
+            }
+        };
+        fold(&h[basis_b(P, Q)], Q, P, &h[basis_bf(P, Q)]);
+        fold(&h[basis_bt(P, Q)], P, Q, &h[basis_btf(P, Q)]);
+        fold(&h[basis_d(P, Q)], Q, Q, &h[basis_df(P, Q)]);
+        fold(&h[basis_dt(P, Q)], Q, Q, &h[basis_dtf(P, Q)]);
         for (size_t i = 0; i < h.size(); ++i) h32[i] = (float)h[i];
         if ((c = check_hip(op, hipMemcpy(op->basis64, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice),
                            "copy basis")))

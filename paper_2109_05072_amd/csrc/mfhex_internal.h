@@ -84,12 +84,12 @@ constexpr int apply_nbuf(int mode) { return mode == 1 ? 3 : 1; }
 // writing each node's chunk as one contiguous run.
 constexpr int kNumVariants = 9;
 constexpr int kVarG[9][5] = {
-    {16, 8, 32, 16, 32}, {8, 4, 16, 8, 16}, {4, 2, 8, 4, 8}, {2, 2, 1, 4, 4}, {1, 2, 1, 2, 4},
-    {2, 1, 1, 1, 2},     {1, 1, 1, 2, 2},   {1, 1, 1, 2, 2}, {1, 1, 1, 2, 2}};
+    {16, 8, 32, 16, 32}, {8, 4, 16, 8, 16}, {4, 2, 8, 4, 8}, {4, 2, 1, 2, 4}, {1, 2, 1, 2, 4},
+    {1, 2, 1, 1, 2},     {1, 1, 1, 2, 2},   {2, 1, 1, 1, 2}, {1, 1, 1, 2, 2}};
 constexpr int kVarNT[9][5] = {
     {64, 64, 64, 128, 128},  {64, 64, 64, 128, 128},  {64, 64, 64, 128, 128},
-    {128, 64, 64, 128, 64},  {128, 64, 64, 128, 128}, {128, 64, 128, 256, 64},
-    {256, 128, 64, 128, 64}, {256, 128, 64, 128, 256}, {256, 128, 64, 128, 256}};
+    {128, 64, 64, 128, 64},  {64, 64, 128, 128, 128}, {64, 128, 128, 256, 64},
+    {128, 256, 64, 128, 64}, {256, 128, 64, 128, 256}, {256, 128, 64, 128, 256}};
 constexpr int variant_vc(int v) { return v < 5 ? 1 : v == 5 ? 2 : v == 6 ? 4 : v == 7 ? 8 : 16; }
 // The mass operator keeps one LDS array per element instead of three and has
 // far less work per element, so at low order its single-vector variants
@@ -109,8 +109,20 @@ constexpr size_t apply_lds(int Q, int mode, int elem_bytes, int v)
     return (size_t)variant_g(Q, v, mode) * variant_vc(v) * apply_nbuf(mode) * lds_buf(Q) * elem_bytes;
 }
 constexpr size_t kMaxLds = 65536;
-// Size of the device basis block in elements: B, B^T (q x p+1 each), D, D^T (q x q each).
-constexpr int basis_len(int P, int Q) { return 2 * Q * P + 2 * Q * Q; }
+// Device basis block (elements): B [Q][P], B^T [P][Q], D [Q][Q], D^T [Q][Q],
+// then the folded (even-odd) forms of the same four matrices: for a matrix M
+// with NO rows and NI columns, row o < ceil(NO/2) holds
+//   [ (M[o][i] + M[o][NI-1-i])/2 for i < NI/2 | (M[o][i] - M[o][NI-1-i])/2 for i < NI/2 | M[o][NI/2] if NI odd ].
+constexpr int half_up(int n) { return (n + 1) / 2; }
+constexpr int basis_b(int, int) { return 0; }
+constexpr int basis_bt(int P, int Q) { return Q * P; }
+constexpr int basis_d(int P, int Q) { return 2 * Q * P; }
+constexpr int basis_dt(int P, int Q) { return 2 * Q * P + Q * Q; }
+constexpr int basis_bf(int P, int Q) { return 2 * Q * P + 2 * Q * Q; }
+constexpr int basis_btf(int P, int Q) { return basis_bf(P, Q) + half_up(Q) * P; }
+constexpr int basis_df(int P, int Q) { return basis_btf(P, Q) + half_up(P) * Q; }
+constexpr int basis_dtf(int P, int Q) { return basis_df(P, Q) + half_up(Q) * Q; }
+constexpr int basis_len(int P, int Q) { return basis_dtf(P, Q) + half_up(Q) * Q; }
 
 // Per-order dispatch (one translation unit per order, apply_p<N>.hip).
 hipError_t launch_apply(const ApplyLaunch &a);

@@ -37,11 +37,12 @@ def kernel_source_hash() -> str:
 
 
 def _short(name: str) -> str:
-    m = re.match(r"void mfhex::k_apply<(\d+), (\d+), (\w+), (\d), (\w+), (\w+), (\d+), (\d+)>", name)
+    m = re.match(r"void mfhex::k_apply<(\d+), (\d+), (\w+), (\d), (\w+), (\w+), (\d+), (\d+)(?:, (\d+))?>", name)
     if m:
-        P, Q, colloc, mode, vark, T, G, NT = m.groups()
+        P, Q, colloc, mode, vark, T, G, NT, VC = m.groups()
         kind = {"0": "mass", "1": "diffusion", "2": "rhs"}[mode]
-        return f"k_apply p={int(P) - 1} q={Q} {kind}{' kappa' if vark == 'true' else ''} {T} G={G} NT={NT}"
+        vc = f" VC={VC}" if VC and VC != "1" else ""
+        return f"k_apply p={int(P) - 1} q={Q} {kind}{' kappa' if vark == 'true' else ''} {T} G={G} NT={NT}{vc}"
     name = name.replace("(anonymous namespace)::", "").replace("void ", "")
     return name.split("(")[0].split("<")[0].split("::")[-1][:60]
 

@@ -50,7 +50,10 @@ def test_query_sizes():
     # vertices + offsets + FP64 and FP32 factors + 1D basis block (B, B^T, D, D^T in FP64
     # and FP32) + flag, each 256-aligned
     al = lambda x: (x + 255) // 256 * 256  # noqa: E731
-    nb = 2 * 4 * 3 + 2 * 4 * 4
+    P, Q = 3, 4
+    h = lambda n: (n + 1) // 2  # noqa: E731
+    # plain B, B^T, D, D^T and their folded (even-odd) half-row forms
+    nb = 2 * Q * P + 2 * Q * Q + h(Q) * P + h(P) * Q + 2 * h(Q) * Q
     expect = (al(4 * 3 * 5 * 3 * 8) + al(24 * 27 * 4) + al(24 * 6 * 64 * 8) + al(24 * 6 * 64 * 4)
               + al(nb * 12 + 256) + 256)
     assert s.workspace_bytes == expect
@@ -104,6 +107,10 @@ def test_library_bases_match_the_mathematics(p, quad):
         np.testing.assert_allclose(xq, nodes, atol=0)
         np.testing.assert_allclose(B, np.eye(p + 1), atol=0)
         assert abs(wq.sum() - 2.0) < 1e-14
+    # nodes and points are symmetric about 0, so B is centro-symmetric and D
+    # anti-centro-symmetric (the kernels evaluate contractions in even-odd form)
+    np.testing.assert_allclose(B[::-1, ::-1], B, atol=1e-14)
+    np.testing.assert_allclose(D[::-1, ::-1], -D, atol=1e-13)
     # D differentiates every polynomial of degree < q on the points exactly
     for k in range(q):
         dk = k * xq ** (k - 1) if k else np.zeros(q)
