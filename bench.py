@@ -121,7 +121,8 @@ def main():
         if args.tune:
             op.tune()
         meta[p] = dict(ne=ne, N=op.n_nodes, E=op.n_elem, q=p + 2, epb=op.get_config())
-        print(f"# setup p={p}: {ne}^3 elements, {op.n_nodes} DOFs, launch (variant, elems, threads) {meta[p]['epb']}",
+        print(f"# setup p={p}: {ne}^3 elements, {op.n_nodes} DOFs, launch (variant, elems, threads, depth) "
+              f"{meta[p]['epb']}",
               file=sys.stderr, flush=True)
 
     for _ in range(args.warmup):
@@ -156,14 +157,19 @@ def main():
                       "alg_gbs": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
                       "alg_tflops": round(alg_flops(m["E"], p, m["q"], args.kind) / (t_ms / 1e3) / 1e12, 2),
                       "launch": {"variant": m["epb"][0], "elements_per_group": m["epb"][1],
-                                 "threads_per_group": m["epb"][2]},
+                                 "threads_per_group": m["epb"][2], "groups_per_block": m["epb"][3]},
                       "paper_v100_cuda_gen_gdofs": PAPER_V100_CUDA_GEN.get(p)})
     dom = max(per_p, key=lambda r: r["ms"])
     from paper_2109_05072_amd.prof_summary import read_traffic
-    traffic = read_traffic(os.path.join(ROOT, "profiles", "bp3_apply_traffic.txt"))
     lg = dom["launch"]
-    dom_name = (f"k_apply p={dom['p']} q={dom['p'] + 2} {args.kind} double G={lg['elements_per_group']} "
-                f"NT={lg['threads_per_group']}")
+    if args.kind == "diffusion":
+        traffic = read_traffic(os.path.join(ROOT, "profiles", "bp3_apply_traffic.txt"))
+        dom_name = (f"k_apply p={dom['p']} q={dom['p'] + 2} diffusion double G={lg['elements_per_group']} "
+                    f"NT={lg['threads_per_group']}")
+    else:
+        traffic = read_traffic(os.path.join(ROOT, "profiles", "bp1_apply_traffic.txt"))
+        dom_name = (f"k_mass p={dom['p']} q={dom['p'] + 2} double G={lg['elements_per_group']} "
+                    f"NT={lg['threads_per_group']}")
     out = {
         "metric": METRIC, "value": round(value, 3), "unit": "GDOF/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
@@ -208,20 +214,23 @@ def sweep_variants(op, x, p, reps=10, nrhs=1):
     y = torch.empty_like(x)
     res = []
     import paper_2109_05072_amd as mf
+    default = op.get_config(nrhs=nrhs)
+    depths = (1, 2, 4) if op.kind == "mass" else (1,)
     for v in range(9):
-        try:
-            op.set_config(v, nrhs=nrhs)
-        except mf.MFHexError:
-            continue
-        op.apply(x, y)
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        for _ in range(reps):
+        for d in depths:
+            try:
+                op.set_config(v, nrhs=nrhs, groups_per_block=d)
+            except mf.MFHexError:
+                continue
             op.apply(x, y)
-        e1.record()
-        torch.cuda.synchronize()
-        res.append((v, op.get_config(nrhs=nrhs)[1:], round(e0.elapsed_time(e1) / reps, 4)))
-    op.set_config(0, nrhs=nrhs)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(reps):
+                op.apply(x, y)
+            e1.record()
+            torch.cuda.synchronize()
+            res.append((v, op.get_config(nrhs=nrhs)[1:], round(e0.elapsed_time(e1) / reps, 4)))
+    op.set_config(default[0], nrhs=nrhs, groups_per_block=default[3])
     print(f"# sweep p={p} nrhs={nrhs}: " + "  ".join(f"v{v} {g}: {ms} ms" for v, g, ms in res), file=sys.stderr,
           flush=True)
 

@@ -182,10 +182,11 @@ int mfhex_cg(mfhex_op op, const double *b_dev, double *x_dev, void *cg_work_dev,
              mfhex_cg_stats *stats, double *rhist, void *stream);
 
 /* Autotune the apply for (prec, nrhs): time every launch variant of the
- * fused kernel (elements per thread group, threads per group) on this
- * operator, reject any whose result differs from the default variant by more
- * than 1e-13 (relative, max norm; 1e-5 for FP32), keep the fastest for this
- * handle and append "<arch> kind quad p nvec prec variant" to the text cache
+ * fused kernel (elements per thread group, threads per group; for the mass
+ * operator also pipeline depths 1, 2 and 4) on this operator, reject any whose
+ * result differs from the default configuration by more than 1e-13 (relative,
+ * max norm; 1e-5 for FP32), keep the fastest for this handle and append
+ * "<arch> kind quad p nvec prec variant depth" to the text cache
  * at cache_path (NULL: no file); handles created later read the file named by
  * the environment variable MFHEX_TUNE_CACHE.  scratch_dev: caller-owned
  * device buffer of at least MFHEX_TUNE_SCRATCH(n_nodes * nvec) bytes
@@ -193,13 +194,19 @@ int mfhex_cg(mfhex_op op, const double *b_dev, double *x_dev, void *cg_work_dev,
 #define MFHEX_TUNE_SCRATCH(len) (3 * ((((size_t)(len)) * 8 + 255) & ~(size_t)255) + 32768)
 int mfhex_tune(mfhex_op op, int prec, int nrhs, void *scratch_dev, const char *cache_path, void *stream);
 
-/* Launch variant the apply uses now for (prec, nrhs), with the elements per
- * thread group and threads per group it stands for (outputs may be NULL). */
+/* Launch configuration the apply uses now for (prec, nrhs): the variant, the
+ * elements per thread group and threads per group it stands for, and the
+ * pipeline depth (element groups one thread group works through in turn,
+ * loading the next group's data while it computes the current one; always 1
+ * for diffusion).  Outputs may be NULL. */
 int mfhex_get_config(mfhex_op op, int prec, int nrhs, int32_t *variant, int32_t *elems_per_group,
-                     int32_t *threads_per_group);
+                     int32_t *threads_per_group, int32_t *groups_per_block);
 
-/* Force the launch variant (0 .. 8; 5 .. 8 carry 2, 4, 8, 16 vectors of a multi-vector together) for (prec, nrhs); MFHEX_ERR_ARG if out of range. */
-int mfhex_set_config(mfhex_op op, int prec, int nrhs, int32_t variant);
+/* Force the launch configuration for (prec, nrhs): variant 0 .. 8 (5 .. 8
+ * carry 2, 4, 8, 16 vectors of a multi-vector together) and pipeline depth
+ * groups_per_block (0: the default, 2 for mass and 1 for diffusion; mass
+ * accepts 1 .. 64, diffusion only 1).  MFHEX_ERR_ARG if out of range. */
+int mfhex_set_config(mfhex_op op, int prec, int nrhs, int32_t variant, int32_t groups_per_block);
 
 /* Static message for a status code; message of the last failure on a
  * handle (NULL op: last failure of a call that had no handle yet). */

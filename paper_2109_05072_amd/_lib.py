@@ -102,8 +102,8 @@ def load(path: str = LIB_PATH):
                       C.POINTER(C.c_double), vp], i32),
         "mfhex_tune": ([vp, i32, i32, vp, C.c_char_p, vp], i32),
         "mfhex_get_config": ([vp, i32, i32, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
-                              C.POINTER(C.c_int32)], i32),
-        "mfhex_set_config": ([vp, i32, i32, C.c_int32], i32),
+                              C.POINTER(C.c_int32), C.POINTER(C.c_int32)], i32),
+        "mfhex_set_config": ([vp, i32, i32, C.c_int32, C.c_int32], i32),
         "mfhex_strerror": ([i32], C.c_char_p),
         "mfhex_last_error": ([vp], C.c_char_p),
         "mfhex_basis_1d": ([i32, i32, i32] + [C.POINTER(C.c_double)] * 5, i32),
@@ -190,14 +190,14 @@ def mfhex_tune(op: int, prec: int, nrhs: int, scratch: int, cache_path, stream: 
 
 
 def mfhex_get_config(op: int, prec: int, nrhs: int):
-    """(variant, elements per group, threads per group)."""
-    v, g, t = C.c_int32(), C.c_int32(), C.c_int32()
-    check(load().mfhex_get_config(op, prec, nrhs, C.byref(v), C.byref(g), C.byref(t)), op)
-    return v.value, g.value, t.value
+    """(variant, elements per group, threads per group, pipeline depth)."""
+    v, g, t, d = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()
+    check(load().mfhex_get_config(op, prec, nrhs, C.byref(v), C.byref(g), C.byref(t), C.byref(d)), op)
+    return v.value, g.value, t.value, d.value
 
 
-def mfhex_set_config(op: int, prec: int, nrhs: int, variant: int) -> None:
-    check(load().mfhex_set_config(op, prec, nrhs, variant), op)
+def mfhex_set_config(op: int, prec: int, nrhs: int, variant: int, groups_per_block: int = 0) -> None:
+    check(load().mfhex_set_config(op, prec, nrhs, variant, groups_per_block), op)
 
 
 def mfhex_strerror(code: int) -> str:

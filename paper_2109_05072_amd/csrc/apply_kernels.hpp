@@ -172,25 +172,32 @@ __device__ __forceinline__ void load_offsets(int32_t (&off)[NR], const int32_t *
     }
 }
 
-// Element values of vectors v0 .. v0+VC-1 into s0 (virtual element g VC + vc).
-// All loads are issued before any is used; masked nodes read node 0 and
-// vectors past nvec read the last vector, and both are zeroed.
-template <int P, int Q, int G, int NT, int VC, typename T, int NR>
-__device__ __forceinline__ void gather(T *s0, const int32_t (&off)[NR], const T *__restrict__ x, int nvec, int v0,
-                                       int tid)
+// Element values of vectors v0 .. v0+VC-1, first into registers (all loads
+// issued before any is used; masked nodes read node 0 and vectors past nvec
+// read the last vector), then into s0 (virtual element g VC + vc), where the
+// masked entries are zeroed.  The halves are separate so that a pipelined
+// kernel can have the next group's loads in flight while it computes.
+template <int P, int G, int NT, int VC, typename T, int NR>
+__device__ __forceinline__ void gather_load(T (&val)[NR], const int32_t (&off)[NR], const T *__restrict__ x, int nvec,
+                                            int v0, int tid)
 {
     static_assert(NR == NodeIO<P, G, NT, VC>::NR, "offset count");
-    using L = Lds<Q>;
-    using IO = NodeIO<P, G, NT, VC>;
-    T val[IO::NR];
 #pragma unroll
-    for (int r = 0; r < IO::NR; ++r) {
+    for (int r = 0; r < NR; ++r) {
         const int vc = (tid + r * NT) % VC;
         const int64_t node = off[r] >= 0 ? off[r] : 0;
         val[r] = x[node * nvec + (v0 + vc < nvec ? v0 + vc : nvec - 1)];
     }
+}
+
+template <int P, int Q, int G, int NT, int VC, typename T, int NR>
+__device__ __forceinline__ void gather_store(T *s0, const T (&val)[NR], const int32_t (&off)[NR], int nvec, int v0,
+                                             int tid)
+{
+    using L = Lds<Q>;
+    using IO = NodeIO<P, G, NT, VC>;
 #pragma unroll
-    for (int r = 0; r < IO::NR; ++r) {
+    for (int r = 0; r < NR; ++r) {
         const int id = tid + r * NT;
         if (id < IO::NID) {
             const int vc = id % VC, gt = id / VC, g = gt / IO::P3, t = gt - g * IO::P3;
@@ -199,6 +206,15 @@ __device__ __forceinline__ void gather(T *s0, const int32_t (&off)[NR], const T 
                 (off[r] >= 0 && v0 + vc < nvec) ? val[r] : T(0);
         }
     }
+}
+
+template <int P, int Q, int G, int NT, int VC, typename T, int NR>
+__device__ __forceinline__ void gather(T *s0, const int32_t (&off)[NR], const T *__restrict__ x, int nvec, int v0,
+                                       int tid)
+{
+    T val[NR];
+    gather_load<P, G, NT, VC>(val, off, x, nvec, v0, tid);
+    gather_store<P, Q, G, NT, VC>(s0, val, off, nvec, v0, tid);
 }
 
 // Transposed restriction: y[node][v0 + vc] += s0 for unmasked nodes.
@@ -249,7 +265,7 @@ __device__ __forceinline__ void grad(T *s0, T *s1, T *s2, const T *__restrict__ 
 }
 
 // ---------------------------------------------------------------------------
-// y += A x  (mass / diffusion), or y += B^T (w detJ f) for the load vector.
+// y += A x  (diffusion), or y += B^T (w detJ f) for the load vector.
 // VC vectors of the multi-vector travel together (virtual elements g*VC + vc).
 // ---------------------------------------------------------------------------
 template <int P, int Q, bool COLLOC, int MODE, bool VARK, typename T, int G, int NT, int VC>
@@ -261,6 +277,7 @@ k_apply(const T *__restrict__ bas, const int64_t nelem, const int nvec, const in
     constexpr int Q2 = Q * Q, Q3 = Q2 * Q;
     constexpr int NPT = G * Q3, RQ = (NPT + NT - 1) / NT;
     constexpr int GV = G * VC;
+    static_assert(MODE != kMass, "the mass operator runs in k_mass");
     using L = Lds<Q>;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T *const s0 = reinterpret_cast<T *>(smem_raw);
@@ -275,7 +292,7 @@ k_apply(const T *__restrict__ bas, const int64_t nelem, const int nvec, const in
     // This lane's geometric factors, loaded once per element group and issued
     // first, so their HBM latency overlaps the gather and the forward
     // contractions, and every chunk of vectors reuses them.
-    constexpr int NQD = MODE == kMass ? 1 : MODE == kDiff ? kQdDiff : 0;
+    constexpr int NQD = MODE == kDiff ? kQdDiff : 0;
     T qv[RQ][NQD > 0 ? NQD : 1];
     if constexpr (NQD > 0) {
 #pragma unroll
@@ -314,20 +331,7 @@ k_apply(const T *__restrict__ bas, const int64_t nelem, const int nvec, const in
             gather<P, Q, G, NT, VC, T>(s0, off, x, nvec, v0, tid);
             group_sync<NT>();
             interp<P, Q, COLLOC, GV, NT, T>(s0, bas, tid);
-            if constexpr (MODE == kMass) {
-#pragma unroll
-                for (int k = 0; k < RQ; ++k) {
-                    const int id = tid + k * NT;
-                    if (id < NPT) {
-                        const int g = id / Q3, pt = id - g * Q3;
-                        const int a = pt % Q, b = (pt / Q) % Q, c = pt / Q2;
-                        const int loc = a + L::PITCH * b + L::PLANE * c;
-#pragma unroll
-                        for (int vc = 0; vc < VC; ++vc) s0[(g * VC + vc) * L::BUF + loc] *= qv[k][0];
-                    }
-                }
-                group_sync<NT>();
-            } else {
+            {
                 grad<P, Q, GV, NT, T>(s0, s1, s2, bas, tid);
 #pragma unroll
                 for (int k = 0; k < RQ; ++k) {
@@ -368,6 +372,104 @@ k_apply(const T *__restrict__ bas, const int64_t nelem, const int nvec, const in
         group_sync<NT>();
         scatter_add<P, Q, G, NT, VC, T>(s0, off, y, nvec, v0, tid);
         group_sync<NT>();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// y += M x  (mass).  A thread group works through `chain` consecutive element
+// groups (and, per group, the chunks of VC vectors) as a software pipeline:
+// the offsets of the next group are loaded when the current one starts, and
+// its point weights (into the registers the current group has just used) and
+// its input values right after the current pointwise scaling, so that their
+// memory latency is hidden by the transposed interpolation and the
+// scatter-add.  With one basis pass each way the mass operator has too little
+// arithmetic per byte to hide that latency otherwise.
+// ---------------------------------------------------------------------------
+template <int Q, int G, int NT, typename T, int RQ>
+__device__ __forceinline__ void load_mass_weights(T (&w)[RQ], const T *__restrict__ qdata, int64_t e0, int64_t nelem,
+                                                  int tid)
+{
+    constexpr int Q3 = Q * Q * Q, NPT = G * Q3;
+#pragma unroll
+    for (int k = 0; k < RQ; ++k) {
+        const int id = tid + k * NT < NPT ? tid + k * NT : NPT - 1;
+        const int g = id / Q3, pt = id - g * Q3;
+        const int64_t e = e0 + g < nelem ? e0 + g : nelem - 1;  // tail group: the last element's (scatters nothing)
+        w[k] = __builtin_nontemporal_load(&qdata[e * Q3 + pt]);
+    }
+}
+
+template <int P, int Q, bool COLLOC, typename T, int G, int NT, int VC>
+__global__ void __launch_bounds__(NT)
+k_mass(const T *__restrict__ bas, const int64_t nelem, const int nvec, const int chain,
+       const int32_t *__restrict__ offsets, const T *__restrict__ qdata, const T *__restrict__ x, T *__restrict__ y)
+{
+    constexpr int Q2 = Q * Q, Q3 = Q2 * Q;
+    constexpr int NPT = G * Q3, RQ = (NPT + NT - 1) / NT;
+    constexpr int GV = G * VC;
+    constexpr int NR = NodeIO<P, G, NT, VC>::NR;
+    using L = Lds<Q>;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T *const s0 = reinterpret_cast<T *>(smem_raw);
+    const int tid = threadIdx.x;
+    const int64_t ngroups = (nelem + G - 1) / G;
+    int64_t grp = xcd_block(blockIdx.x, gridDim.x) * chain;
+    const int64_t gend = grp + chain < ngroups ? grp + chain : ngroups;
+
+    int32_t off[NR], offn[NR];
+    load_offsets<P, G, NT, VC>(off, offsets, grp * G, nelem, tid);
+    T w[RQ], xv[NR];
+    load_mass_weights<Q, G, NT>(w, qdata, grp * G, nelem, tid);
+    gather_load<P, G, NT, VC>(xv, off, x, nvec, 0, tid);
+
+    for (int v0 = 0;;) {
+        // the next work item: the next chunk of vectors, else the next group
+        int nv0 = v0 + VC;
+        int64_t ngrp = grp;
+        if (nv0 >= nvec) {
+            nv0 = 0;
+            ngrp = grp + 1;
+        }
+        const bool more = ngrp < gend, newgrp = more && ngrp != grp;
+        if (newgrp) load_offsets<P, G, NT, VC>(offn, offsets, ngrp * G, nelem, tid);
+        gather_store<P, Q, G, NT, VC>(s0, xv, off, nvec, v0, tid);
+        group_sync<NT>();
+        // the next chunk of the same group needs no new offsets: load it now
+        if (more && !newgrp) gather_load<P, G, NT, VC>(xv, off, x, nvec, nv0, tid);
+        interp<P, Q, COLLOC, GV, NT, T>(s0, bas, tid);
+#pragma unroll
+        for (int k = 0; k < RQ; ++k) {
+            const int id = tid + k * NT;
+            if (id < NPT) {
+                const int g = id / Q3, pt = id - g * Q3;
+                const int a = pt % Q, b = (pt / Q) % Q, c = pt / Q2;
+                const int loc = a + L::PITCH * b + L::PLANE * c;
+#pragma unroll
+                for (int vc = 0; vc < VC; ++vc) s0[(g * VC + vc) * L::BUF + loc] *= w[k];
+            }
+        }
+        group_sync<NT>();
+        if (newgrp) {
+            load_mass_weights<Q, G, NT>(w, qdata, ngrp * G, nelem, tid);
+            gather_load<P, G, NT, VC>(xv, offn, x, nvec, 0, tid);
+        }
+        if constexpr (!COLLOC) {
+            contract<2, Q, Q, Q, P, GV, NT, Q, 1>(s0, s0, bas + basis_btf(P, Q), tid);
+            group_sync<NT>();
+            contract<1, Q, Q, P, P, GV, NT, Q, 1>(s0, s0, bas + basis_btf(P, Q), tid);
+            group_sync<NT>();
+            contract<0, Q, P, P, P, GV, NT, Q, 1>(s0, s0, bas + basis_btf(P, Q), tid);
+        }
+        group_sync<NT>();
+        scatter_add<P, Q, G, NT, VC, T>(s0, off, y, nvec, v0, tid);
+        group_sync<NT>();
+        if (!more) break;
+        if (newgrp) {
+#pragma unroll
+            for (int r = 0; r < NR; ++r) off[r] = offn[r];
+        }
+        grp = ngrp;
+        v0 = nv0;
     }
 }
 
@@ -444,6 +546,14 @@ static hipError_t launch_apply_v(const ApplyLaunch &a)
     if constexpr ((VC > 1 && (MODE == kRhs || VARK)) || lds > kMaxLds) {
         (void)a;
         return hipErrorInvalidValue;
+    } else if constexpr (MODE == kMass) {
+        const int chain = a.chain > 0 ? a.chain : 1;
+        const int64_t nblk = ((a.v.nelem + G - 1) / G + chain - 1) / chain;
+        auto kern = k_mass<P, Q, COLLOC, T, G, NT, VC>;
+        hipLaunchKernelGGL(kern, dim3((unsigned)nblk), dim3(NT), lds, a.stream, static_cast<const T *>(a.basis_dev),
+                           a.v.nelem, a.nvec, chain, a.v.offsets, static_cast<const T *>(a.v.qdata),
+                           static_cast<const T *>(a.x), static_cast<T *>(a.y));
+        return hipGetLastError();
     } else {
         const int64_t nblk = (a.v.nelem + G - 1) / G;
         auto kern = k_apply<P, Q, COLLOC, MODE, VARK, T, G, NT, VC>;

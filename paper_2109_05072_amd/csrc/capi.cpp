@@ -3,6 +3,7 @@
 // arguments, carves the caller's workspace and enqueues work on the caller's
 // stream.
 #include <climits>
+#include <cstdlib>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
@@ -145,11 +146,19 @@ int default_variant(const mfhex_op_s &op, int prec, int nvec)
     return 0;
 }
 
-int variant_for(const mfhex_op_s &op, int prec, int nvec)
+// Pipeline depth: the mass kernel chains two element groups per thread group
+// by default (measured fastest on the benchmark meshes); the diffusion kernel
+// takes one.
+int default_chain(const mfhex_op_s &op) { return mode_of(op) == kMass ? 2 : 1; }
+
+LaunchCfg config_for(const mfhex_op_s &op, int prec, int nvec)
 {
-    auto it = op.variant.find({prec, nvec});
-    if (it != op.variant.end()) return it->second;
-    return default_variant(op, prec, nvec);
+    auto it = op.config.find({prec, nvec});
+    if (it != op.config.end()) return it->second;
+    LaunchCfg c;
+    c.variant = default_variant(op, prec, nvec);
+    c.chain = default_chain(op);
+    return c;
 }
 
 hipError_t launch_apply(const ApplyLaunch &a)
@@ -198,7 +207,7 @@ static OpView view_of(const mfhex_op_s &op, int prec)
     return v;
 }
 
-int apply_impl(mfhex_op op, int prec, int nrhs, const void *x, void *y, hipStream_t s, bool zero, int variant)
+int apply_impl(mfhex_op op, int prec, int nrhs, const void *x, void *y, hipStream_t s, bool zero, int variant, int chain)
 {
     if (!op) return set_error(nullptr, MFHEX_ERR_ARG, "null handle");
     if (prec != MFHEX_F64 && prec != MFHEX_F32) return set_error(op, MFHEX_ERR_ARG, "prec must be F64 or F32");
@@ -213,8 +222,12 @@ int apply_impl(mfhex_op op, int prec, int nrhs, const void *x, void *y, hipStrea
     const size_t bytes = (size_t)op->N * nvec * (prec == MFHEX_F32 ? 4 : 8);
     const uintptr_t xa = (uintptr_t)x, ya = (uintptr_t)y;
     if (xa < ya + bytes && ya < xa + bytes) return set_error(op, MFHEX_ERR_ARG, "x and y overlap");
-    const int var = variant >= 0 ? variant : variant_for(*op, prec, nvec);
+    const LaunchCfg cfg = config_for(*op, prec, nvec);
+    const int var = variant >= 0 ? variant : cfg.variant;
     if (!valid_variant(*op, prec, var)) return set_error(op, MFHEX_ERR_ARG, "invalid launch variant");
+    const int nchain = chain > 0 ? chain : cfg.chain;
+    if (nchain > kMaxChain || (nchain > 1 && mode_of(*op) != kMass))
+        return set_error(op, MFHEX_ERR_ARG, "invalid pipeline depth");
     if (zero) {
         const int c = check_hip(op, hipMemsetAsync(y, 0, bytes, s), "hipMemsetAsync");
         if (c) return c;
@@ -229,6 +242,7 @@ int apply_impl(mfhex_op op, int prec, int nrhs, const void *x, void *y, hipStrea
     a.vark = op->d.variable_kappa;
     a.nvec = nvec;
     a.variant = var;
+    a.chain = nchain;
     a.x = x;
     a.y = y;
     a.wdet = nullptr;
@@ -472,21 +486,28 @@ int mfhex_tune(mfhex_op op, int prec, int nrhs, void *scratch_dev, const char *c
 }
 
 int mfhex_get_config(mfhex_op op, int prec, int nrhs, int32_t *variant, int32_t *elems_per_group,
-                     int32_t *threads_per_group)
+                     int32_t *threads_per_group, int32_t *groups_per_block)
 {
     if (!op || nrhs < 1) return fail(MFHEX_ERR_ARG, "bad argument");
-    const int v = variant_for(*op, prec, nrhs * op->d.ncomp);
-    if (variant) *variant = v;
-    if (elems_per_group) *elems_per_group = variant_g(op->Q, v, mode_of(*op));
-    if (threads_per_group) *threads_per_group = variant_nt(op->Q, v);
+    const LaunchCfg c = config_for(*op, prec, nrhs * op->d.ncomp);
+    if (variant) *variant = c.variant;
+    if (elems_per_group) *elems_per_group = variant_g(op->Q, c.variant, mode_of(*op));
+    if (threads_per_group) *threads_per_group = variant_nt(op->Q, c.variant);
+    if (groups_per_block) *groups_per_block = c.chain;
     return MFHEX_OK;
 }
 
-int mfhex_set_config(mfhex_op op, int prec, int nrhs, int32_t variant)
+int mfhex_set_config(mfhex_op op, int prec, int nrhs, int32_t variant, int32_t groups_per_block)
 {
     if (!op || nrhs < 1) return fail(MFHEX_ERR_ARG, "bad argument");
     if (!valid_variant(*op, prec, variant)) return set_error(op, MFHEX_ERR_ARG, "invalid launch variant");
-    op->variant[{prec, nrhs * op->d.ncomp}] = variant;
+    const int chain = groups_per_block > 0 ? groups_per_block : default_chain(*op);
+    if (groups_per_block < 0 || chain > kMaxChain || (chain > 1 && mode_of(*op) != kMass))
+        return set_error(op, MFHEX_ERR_ARG, "invalid pipeline depth");
+    LaunchCfg c;
+    c.variant = variant;
+    c.chain = chain;
+    op->config[{prec, nrhs * op->d.ncomp}] = c;
     return MFHEX_OK;
 }
 

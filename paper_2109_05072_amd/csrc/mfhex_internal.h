@@ -45,6 +45,15 @@ struct OpView {
 
 enum Mode : int { kMass = 0, kDiff = 1, kRhs = 2 };
 
+// Launch configuration of the apply: the variant (elements and threads per
+// thread group, vectors per chunk) and, for the mass operator, the number of
+// consecutive element groups one thread group pipelines through.
+constexpr int kMaxChain = 64;
+struct LaunchCfg {
+    int variant = 0;
+    int chain = 1;
+};
+
 struct ApplyLaunch {
     OpView v;
     int P, colloc;
@@ -54,6 +63,7 @@ struct ApplyLaunch {
     int vark;             // multiply the factors by kappa
     int nvec;
     int variant;          // launch variant (elements and threads per group)
+    int chain;            // mass: element groups per thread group (software pipeline depth), >= 1
     const void *x;        // input (for kRhs: the per-point f, FP64)
     void *y;              // output (accumulated)
     const double *wdet;   // kRhs: w*detJ per point

@@ -24,7 +24,7 @@ struct mfhex_op_s {
     double *basis64 = nullptr;  // device basis block, FP64 and FP32
     float *basis32 = nullptr;
     bool kappa_set = false;
-    std::map<std::pair<int, int>, int> variant;  // (prec, nvec) -> launch variant
+    std::map<std::pair<int, int>, mfhex::LaunchCfg> config;  // (prec, nvec) -> apply launch configuration
     std::string err;
     double *pinned = nullptr;  // small pinned host buffer for solver scalars
 };
@@ -48,10 +48,13 @@ int set_error(mfhex_op op, int code, const std::string &msg);
 int check_hip(mfhex_op op, hipError_t e, const char *what);
 
 // Internal apply: y (+)= A x on `s` with an explicit configuration.
-int apply_impl(mfhex_op op, int prec, int nrhs, const void *x, void *y, hipStream_t s, bool zero, int variant);
+// variant < 0 / chain <= 0: the handle's configuration for (prec, nvec).
+int apply_impl(mfhex_op op, int prec, int nrhs, const void *x, void *y, hipStream_t s, bool zero, int variant = -1,
+               int chain = 0);
 int default_variant(const mfhex_op_s &op, int prec, int nvec);
 bool valid_variant(const mfhex_op_s &op, int prec, int variant);
-int variant_for(const mfhex_op_s &op, int prec, int nvec);
+LaunchCfg config_for(const mfhex_op_s &op, int prec, int nvec);
+int default_chain(const mfhex_op_s &op);
 int mode_of(const mfhex_op_s &op);
 
 int cg_solve(mfhex_op op, const double *b, double *x, void *work, const mfhex_cg_opts *o, mfhex_cg_stats *st,

@@ -1,13 +1,15 @@
 // Autotuner for the fused apply: per (operator, precision, number of vectors)
-// pick the launch variant (elements and threads per group) by measurement.
+// pick the launch variant (elements and threads per group) and, for the mass
+// operator, the pipeline depth (element groups per thread group) by
+// measurement.
 //
 // Every candidate is first checked against the default configuration on a
 // random input (max-norm relative difference <= 1e-13 in FP64, 1e-5 in FP32;
 // candidates only change the grouping of elements and lanes, so anything
 // larger is a bug and the candidate is dropped), then timed with HIP events
 // over repeated applies.  The winner is kept on the handle and appended to a
-// text cache "<arch> kind quad p nvec prec variant", which later handles read
-// from the file named by MFHEX_TUNE_CACHE.  This plays the role of the
+// text cache "<arch> kind quad p nvec prec variant depth", which later
+// handles read from the file named by MFHEX_TUNE_CACHE.  This plays the role of the
 // offline benchmark sweeps that select kernel variants per problem shape
 // (Sec. 2, the MAGMA batched kernels chosen from tuning tables).
 #include <cstdio>
@@ -41,11 +43,18 @@ void load_tune_cache(mfhex_op op)
     FILE *f = std::fopen(path, "r");
     if (!f) return;
     const std::string arch = arch_name(op->device);
-    char a[64];
-    int kind, quad, p, nvec, prec, epb;
-    while (std::fscanf(f, "%63s %d %d %d %d %d %d", a, &kind, &quad, &p, &nvec, &prec, &epb) == 7) {
-        if (arch == a && kind == op->d.kind && quad == op->d.quad && p == op->d.p && valid_variant(*op, prec, epb))
-            op->variant[{prec, nvec}] = epb;
+    char line[256], a[64];
+    while (std::fgets(line, sizeof line, f)) {
+        int kind, quad, p, nvec, prec, epb, depth;
+        if (std::sscanf(line, "%63s %d %d %d %d %d %d %d", a, &kind, &quad, &p, &nvec, &prec, &epb, &depth) != 8)
+            continue;
+        if (arch != a || kind != op->d.kind || quad != op->d.quad || p != op->d.p || !valid_variant(*op, prec, epb))
+            continue;
+        if (depth < 1 || depth > kMaxChain || (depth > 1 && mode_of(*op) != kMass)) continue;
+        LaunchCfg c;
+        c.variant = epb;
+        c.chain = depth;
+        op->config[{prec, nvec}] = c;
     }
     std::fclose(f);
 }
@@ -75,26 +84,35 @@ int tune(mfhex_op op, int prec, int nrhs, void *scratch, const char *cache_path,
         if ((c = check_hip(op, hipMemcpyAsync(x64, ytest, len * es, hipMemcpyDeviceToDevice, s), "copy"))) return cleanup(c);
     }
     const int def = default_variant(*op, prec, nvec);
-    if ((c = apply_impl(op, prec, nrhs, x, yref, s, true, def))) return cleanup(c);
-    std::vector<int> cand;
+    if ((c = apply_impl(op, prec, nrhs, x, yref, s, true, def, default_chain(*op)))) return cleanup(c);
+    std::vector<LaunchCfg> cand;
+    const std::vector<int> depths = mode_of(*op) == kMass ? std::vector<int>{1, 2, 4} : std::vector<int>{1};
     for (int e = 0; e < kNumVariants; ++e)
-        if (valid_variant(*op, prec, e)) cand.push_back(e);
+        if (valid_variant(*op, prec, e))
+            for (int d : depths) {
+                LaunchCfg k;
+                k.variant = e;
+                k.chain = d;
+                cand.push_back(k);
+            }
     hipEvent_t e0, e1;
     if ((c = check_hip(op, hipEventCreate(&e0), "hipEventCreate"))) return cleanup(c);
     if ((c = check_hip(op, hipEventCreate(&e1), "hipEventCreate"))) return cleanup(c);
     const int reps = 10;
-    int best = def;
+    LaunchCfg best;
+    best.variant = def;
+    best.chain = default_chain(*op);
     float best_ms = 1e30f;
     const double tol = prec == MFHEX_F32 ? 1e-5 : 1e-13;
-    for (int epb : cand) {
-        if ((c = apply_impl(op, prec, nrhs, x, ytest, s, true, epb))) break;
+    for (const LaunchCfg &k : cand) {
+        if ((c = apply_impl(op, prec, nrhs, x, ytest, s, true, k.variant, k.chain))) break;
         if ((c = check_hip(op, launch_relmaxdiff(ytest, yref, len, prec, partial, out2, s), "diff kernel"))) break;
         double h[2];
         if ((c = check_hip(op, hipMemcpyAsync(h, out2, 2 * sizeof(double), hipMemcpyDeviceToHost, s), "copy"))) break;
         if ((c = check_hip(op, hipStreamSynchronize(s), "sync"))) break;
         if (!(h[0] <= tol * h[1])) continue;  // wrong result: reject the candidate
         if ((c = check_hip(op, hipEventRecord(e0, s), "event"))) break;
-        for (int r = 0; r < reps && !c; ++r) c = apply_impl(op, prec, nrhs, x, ytest, s, true, epb);
+        for (int r = 0; r < reps && !c; ++r) c = apply_impl(op, prec, nrhs, x, ytest, s, true, k.variant, k.chain);
         if (c) break;
         if ((c = check_hip(op, hipEventRecord(e1, s), "event"))) break;
         if ((c = check_hip(op, hipEventSynchronize(e1), "event"))) break;
@@ -102,18 +120,18 @@ int tune(mfhex_op op, int prec, int nrhs, void *scratch, const char *cache_path,
         (void)hipEventElapsedTime(&ms, e0, e1);
         if (ms < best_ms) {
             best_ms = ms;
-            best = epb;
+            best = k;
         }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (c) return cleanup(c);
-    op->variant[{prec, nvec}] = best;
+    op->config[{prec, nvec}] = best;
     if (cache_path && *cache_path) {
         FILE *f = std::fopen(cache_path, "a");
         if (f) {
-            std::fprintf(f, "%s %d %d %d %d %d %d\n", arch_name(op->device).c_str(), op->d.kind, op->d.quad, op->d.p,
-                         nvec, prec, best);
+            std::fprintf(f, "%s %d %d %d %d %d %d %d\n", arch_name(op->device).c_str(), op->d.kind, op->d.quad, op->d.p,
+                         nvec, prec, best.variant, best.chain);
             std::fclose(f);
         }
     }

@@ -184,8 +184,9 @@ class Operator:
         return self.get_config(dtype, nrhs)
 
     def get_config(self, dtype=torch.float64, nrhs: int = 1):
-        """(variant, elements per group, threads per group) of the apply launch."""
+        """(variant, elements per group, threads per group, pipeline depth) of the apply launch."""
         return L.mfhex_get_config(self.handle, _prec(dtype), nrhs)
 
-    def set_config(self, variant: int, dtype=torch.float64, nrhs: int = 1) -> None:
-        L.mfhex_set_config(self.handle, _prec(dtype), nrhs, variant)
+    def set_config(self, variant: int, dtype=torch.float64, nrhs: int = 1, groups_per_block: int = 0) -> None:
+        """Force the launch variant and (mass only) the pipeline depth; 0 keeps the default depth."""
+        L.mfhex_set_config(self.handle, _prec(dtype), nrhs, variant, groups_per_block)

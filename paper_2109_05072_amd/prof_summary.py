@@ -43,6 +43,11 @@ def _short(name: str) -> str:
         kind = {"0": "mass", "1": "diffusion", "2": "rhs"}[mode]
         vc = f" VC={VC}" if VC and VC != "1" else ""
         return f"k_apply p={int(P) - 1} q={Q} {kind}{' kappa' if vark == 'true' else ''} {T} G={G} NT={NT}{vc}"
+    m = re.match(r"void mfhex::k_mass<(\d+), (\d+), (\w+), (\w+), (\d+), (\d+), (\d+)>", name)
+    if m:
+        P, Q, colloc, T, G, NT, VC = m.groups()
+        vc = f" VC={VC}" if VC != "1" else ""
+        return f"k_mass p={int(P) - 1} q={Q} {T} G={G} NT={NT}{vc}"
     name = name.replace("(anonymous namespace)::", "").replace("void ", "")
     return name.split("(")[0].split("<")[0].split("::")[-1][:60]
 
@@ -93,7 +98,7 @@ def traffic_summary(fetch_dir: str, write_dir: str, command: str) -> str:
            f"scale fetch x{f_scale:.4f}, write x{w_scale:.4f}",
            f"{'kernel':<60} {'fetch_KiB':>12} {'write_KiB':>12} {'traffic_bytes':>15} {'avg_us':>9}"]
     for k in fe:
-        if "k_apply" not in k or k not in wr:
+        if ("k_apply" not in k and "k_mass" not in k) or k not in wr:
             continue
         f = sum(fe[k]) / len(fe[k])
         w = sum(wr[k]) / len(wr[k])
@@ -112,7 +117,7 @@ def read_traffic(path: str):
         return {}
     res = {}
     for line in txt.splitlines():
-        if line.startswith("k_apply"):
+        if line.startswith("k_apply") or line.startswith("k_mass"):
             parts = line.split()
             name = " ".join(parts[:-4])
             res[name] = float(parts[-2])

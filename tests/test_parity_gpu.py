@@ -81,11 +81,15 @@ def test_apply_fp64_matches_oracle(gpu_lib, p, kind, quad, dirichlet):
     yo = oracle.apply(pr, x)
     y = host(op.apply(dev(x)))
     assert relerr(y, yo) <= TOL64
+    # mass: thread groups that pipeline 1, 2, 3 or 7 element groups (30 elements:
+    # the last thread group of the odd depths gets a ragged share)
+    depths = (1, 2, 3, 7) if kind == "mass" else (0,)
     for v in valid_variants(op):
-        op.set_config(v)
-        _say("apply64 variant", v, op.get_config())
-        y2 = host(op.apply(dev(x)))
-        assert relerr(y2, yo) <= TOL64
+        for d in depths:
+            op.set_config(v, groups_per_block=d)
+            _say("apply64 variant", v, op.get_config())
+            y2 = host(op.apply(dev(x)))
+            assert relerr(y2, yo) <= TOL64
 
 
 @pytest.mark.parametrize("p", [1, 3, 5, 8])
@@ -120,6 +124,41 @@ def test_multivector_matches_oracle_and_looped(gpu_lib, p, ncomp, nrhs, quad):
         for v in range(nvec):
             yv = host(single.apply(dev(x[:, v].copy())))
             assert relerr(y[:, v], yv) <= 1e-14
+
+
+@pytest.mark.parametrize("p,ncomp,nrhs", [(2, 3, 2), (4, 1, 5), (7, 3, 1)])
+def test_mass_multivector_pipeline_matches_oracle(gpu_lib, p, ncomp, nrhs):
+    """Chunks of vectors and pipelined element groups together: the next work
+    item is either the next chunk of the same group or the next group."""
+    _say("mass multivector", p, ncomp, nrhs)
+    op, pr = build(gpu_lib, 3, 2, 3, p, "mass", "gauss", False, ncomp=ncomp)
+    nvec = ncomp * nrhs
+    x = synth.uniform_vector(pr.n_nodes, nvec=nvec)
+    yo = oracle.apply(pr, x)
+    for v in valid_variants(op, nrhs=nrhs):
+        for d in (1, 2, 5):
+            op.set_config(v, nrhs=nrhs, groups_per_block=d)
+            _say("mass multivector config", op.get_config(nrhs=nrhs))
+            assert relerr(host(op.apply(dev(x))), yo) <= TOL64
+
+
+def test_pipeline_depth_configuration(gpu_lib):
+    from paper_2109_05072_amd import _lib as L
+    diff, _ = build(gpu_lib, 2, 2, 2, 3, "diffusion", "gauss")
+    mass, _ = build(gpu_lib, 2, 2, 2, 3, "mass", "gauss", False)
+    assert diff.get_config()[3] == 1
+    assert mass.get_config()[3] == 2
+    diff.set_config(0, groups_per_block=1)
+    for bad in (2, 65, -1):
+        with pytest.raises(L.MFHexError):
+            diff.set_config(0, groups_per_block=bad)
+    for bad in (65, -1):
+        with pytest.raises(L.MFHexError):
+            mass.set_config(0, groups_per_block=bad)
+    mass.set_config(1, groups_per_block=64)
+    assert mass.get_config()[0] == 1 and mass.get_config()[3] == 64
+    mass.set_config(1, groups_per_block=0)
+    assert mass.get_config()[3] == 2
 
 
 def test_apply_add_accumulates(gpu_lib):
@@ -203,8 +242,20 @@ def test_every_launch_configuration_agrees(gpu_lib, p, quad, nrhs):
     with pytest.raises(L.MFHexError):
         op.set_config(9, nrhs=nrhs)
     best = op.tune(nrhs=nrhs)
-    assert best[0] in vs
+    assert best[0] in vs and best[3] == 1
     assert relerr(host(op.apply(x)), ref) <= 1e-13
+
+
+def test_tuner_picks_a_mass_pipeline_depth(gpu_lib, tmp_path):
+    op, pr = build(gpu_lib, 4, 4, 3, 4, "mass", "gauss", False)
+    x = dev(synth.uniform_vector(pr.n_nodes))
+    ref = host(op.apply(x))
+    cache = tmp_path / "tune.txt"
+    best = op.tune(cache_path=str(cache))
+    assert best[3] in (1, 2, 4)
+    assert relerr(host(op.apply(x)), ref) <= 1e-13
+    fields = cache.read_text().split()
+    assert len(fields) == 8 and int(fields[6]) == best[0] and int(fields[7]) == best[3]
 
 
 # --- coefficient gradient -------------------------------------------------------------------
