@@ -209,19 +209,27 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-def sweep_variants(op, x, p, reps=10, nrhs=1):
+def sweep_variants(op, x, p, reps=10, rounds=3, nrhs=1):
+    """Median over interleaved rounds of the apply time of every launch configuration (stderr)."""
     import torch
-    y = torch.empty_like(x)
-    res = []
     import paper_2109_05072_amd as mf
+    y = torch.empty_like(x)
     default = op.get_config(nrhs=nrhs)
     depths = (1, 2, 4) if op.kind == "mass" else (1,)
+    cfgs = []
     for v in range(9):
         for d in depths:
             try:
                 op.set_config(v, nrhs=nrhs, groups_per_block=d)
             except mf.MFHexError:
                 continue
+            cfgs.append((v, d, op.get_config(nrhs=nrhs)[1:]))
+            for _ in range(3):
+                op.apply(x, y)
+    times = {c[:2]: [] for c in cfgs}
+    for _ in range(rounds):
+        for v, d, _g in cfgs:
+            op.set_config(v, nrhs=nrhs, groups_per_block=d)
             op.apply(x, y)
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             e0.record()
@@ -229,10 +237,11 @@ def sweep_variants(op, x, p, reps=10, nrhs=1):
                 op.apply(x, y)
             e1.record()
             torch.cuda.synchronize()
-            res.append((v, op.get_config(nrhs=nrhs)[1:], round(e0.elapsed_time(e1) / reps, 4)))
+            times[(v, d)].append(e0.elapsed_time(e1) / reps)
     op.set_config(default[0], nrhs=nrhs, groups_per_block=default[3])
-    print(f"# sweep p={p} nrhs={nrhs}: " + "  ".join(f"v{v} {g}: {ms} ms" for v, g, ms in res), file=sys.stderr,
-          flush=True)
+    res = sorted(((float(np.median(times[(v, d)])), v, g) for v, d, g in cfgs))
+    print(f"# sweep p={p} nrhs={nrhs} (median of {rounds}): " + "  ".join(f"v{v} {g}: {ms:.4f} ms" for ms, v, g in res),
+          file=sys.stderr, flush=True)
 
 
 def _time(fn, reps=5):

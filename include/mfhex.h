@@ -204,8 +204,9 @@ int mfhex_get_config(mfhex_op op, int prec, int nrhs, int32_t *variant, int32_t 
 
 /* Force the launch configuration for (prec, nrhs): variant 0 .. 8 (5 .. 8
  * carry 2, 4, 8, 16 vectors of a multi-vector together) and pipeline depth
- * groups_per_block (0: the default, 2 for mass and 1 for diffusion; mass
- * accepts 1 .. 64, diffusion only 1).  MFHEX_ERR_ARG if out of range. */
+ * groups_per_block (0: the operator's default, measured per order for mass
+ * and 1 for diffusion; mass accepts 1 .. 64, diffusion only 1).
+ * MFHEX_ERR_ARG if out of range. */
 int mfhex_set_config(mfhex_op op, int prec, int nrhs, int32_t variant, int32_t groups_per_block);
 
 /* Static message for a status code; message of the last failure on a

@@ -145,38 +145,93 @@ __device__ __forceinline__ void contract(const T *src, T *dst, const T *__restri
     }
 }
 
-// Restriction and its transpose work on (node, vector) pairs numbered with
-// the vector fastest: id = (g P^3 + t) VC + vc.  With a chunk of VC vectors,
-// consecutive lanes then touch consecutive doubles of one node's run, so a
-// gather instruction reads whole cache lines and a scatter-add instruction
-// updates whole lines at once instead of hitting the same line VC times.
+// Element groups.  The G elements of a group are consecutive in one x-row of
+// elements (the last group of a row may hold fewer), so elements g and g+1
+// share their face i = P-1 / i = 0.
+struct GroupPos {
+    int64_t e0;  // first element
+    int nvalid;  // elements of the group inside the row
+};
+
+template <int G>
+__device__ __forceinline__ GroupPos group_pos(int64_t grp, int nex)
+{
+    GroupPos gp;
+    if constexpr (G == 1) {
+        gp.e0 = grp;
+        gp.nvalid = 1;
+    } else {
+        const int64_t gpr = (nex + G - 1) / G;  // groups per row
+        const int64_t row = grp / gpr, ex0 = (grp - row * gpr) * G;
+        gp.e0 = row * nex + ex0;
+        gp.nvalid = (int)(nex - ex0 < G ? nex - ex0 : G);
+    }
+    return gp;
+}
+
+// Restriction and its transpose work on the distinct nodes of a group: P^2
+// lines along x of W = G(P-1)+1 nodes, node u = (j + P k) W + X with X the
+// position along the line, and with VC vectors the pair id = u VC + vc
+// (vector fastest).  Consecutive lanes then touch consecutive doubles of one
+// line of x and y, so a gather instruction reads whole cache lines and a
+// scatter-add instruction updates them with few requests; a node on a face
+// shared inside the group is read once and updated once (its two element
+// values are summed on chip first), which saves atomic traffic.
 template <int P, int G, int NT, int VC>
 struct NodeIO {
     static constexpr int P3 = P * P * P;
-    static constexpr int NID = G * P3 * VC;
+    static constexpr int W = G * (P - 1) + 1;  // nodes per x-line of a full group
+    static constexpr int NID = W * P * P * VC;
     static constexpr int NR = (NID + NT - 1) / NT;  // (node, vector) pairs per lane
 };
 
-// off[r] = global node of pair tid + r NT, or -1 (masked, past the group, past nelem).
+// Element g and its local x index i of position X on a line of a group of nvalid elements.
+template <int P, int G>
+__device__ __forceinline__ void line_pos(int X, int nvalid, int &g, int &i)
+{
+    if constexpr (G == 1) {
+        g = 0;
+        i = X;
+    } else {
+        g = X / (P - 1);
+        if (g > nvalid - 1) g = nvalid - 1;
+        i = X - g * (P - 1);
+    }
+}
+
+// Positions X <= nvalid (P-1) of a line belong to the group's elements.
+template <int P, int G>
+__device__ __forceinline__ bool line_valid(int X, int nvalid)
+{
+    if constexpr (G == 1) return true;
+    else return X <= nvalid * (P - 1);
+}
+
+// off[r] = global node of pair tid + r NT, or -1 (masked node, or past the group).
 template <int P, int G, int NT, int VC, int NR>
 __device__ __forceinline__ void load_offsets(int32_t (&off)[NR], const int32_t *__restrict__ offsets, int64_t e0,
-                                             int64_t nelem, int tid)
+                                             int nvalid, int tid)
 {
     static_assert(NR == NodeIO<P, G, NT, VC>::NR, "offset count");
     using IO = NodeIO<P, G, NT, VC>;
 #pragma unroll
-    for (int r = 0; r < IO::NR; ++r) {
+    for (int r = 0; r < NR; ++r) {
         const int id = tid + r * NT;
-        const int gt = id / VC, g = gt / IO::P3;
-        off[r] = (id < IO::NID && e0 + g < nelem) ? offsets[e0 * IO::P3 + gt] : -1;
+        const int u = id / VC, line = u / IO::W, X = u - line * IO::W;
+        int g, i;
+        line_pos<P, G>(X, nvalid, g, i);
+        const int j = line % P, k = line / P;
+        off[r] = (id < IO::NID && line_valid<P, G>(X, nvalid)) ? offsets[(e0 + g) * IO::P3 + i + P * (j + P * k)] : -1;
     }
 }
 
 // Element values of vectors v0 .. v0+VC-1, first into registers (all loads
 // issued before any is used; masked nodes read node 0 and vectors past nvec
-// read the last vector), then into s0 (virtual element g VC + vc), where the
-// masked entries are zeroed.  The halves are separate so that a pipelined
-// kernel can have the next group's loads in flight while it computes.
+// read the last vector), then into s0 (virtual element g VC + vc; a shared
+// face node into both elements), where the masked entries are zeroed.  The
+// halves are separate so that a pipelined kernel can have the next group's
+// loads in flight while it computes.  Elements past nvalid are left unset:
+// they are computed on but never scattered.
 template <int P, int G, int NT, int VC, typename T, int NR>
 __device__ __forceinline__ void gather_load(T (&val)[NR], const int32_t (&off)[NR], const T *__restrict__ x, int nvec,
                                             int v0, int tid)
@@ -192,48 +247,56 @@ __device__ __forceinline__ void gather_load(T (&val)[NR], const int32_t (&off)[N
 
 template <int P, int Q, int G, int NT, int VC, typename T, int NR>
 __device__ __forceinline__ void gather_store(T *s0, const T (&val)[NR], const int32_t (&off)[NR], int nvec, int v0,
-                                             int tid)
+                                             int nvalid, int tid)
 {
     using L = Lds<Q>;
     using IO = NodeIO<P, G, NT, VC>;
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
         const int id = tid + r * NT;
-        if (id < IO::NID) {
-            const int vc = id % VC, gt = id / VC, g = gt / IO::P3, t = gt - g * IO::P3;
-            const int i = t % P, j = (t / P) % P, k = t / (P * P);
-            s0[(g * VC + vc) * L::BUF + i + L::PITCH * j + L::PLANE * k] =
-                (off[r] >= 0 && v0 + vc < nvec) ? val[r] : T(0);
+        const int vc = id % VC, u = id / VC, line = u / IO::W, X = u - line * IO::W;
+        if (id < IO::NID && line_valid<P, G>(X, nvalid)) {
+            int g, i;
+            line_pos<P, G>(X, nvalid, g, i);
+            const int jk = L::PITCH * (line % P) + L::PLANE * (line / P);
+            const T v = (off[r] >= 0 && v0 + vc < nvec) ? val[r] : T(0);
+            s0[(g * VC + vc) * L::BUF + i + jk] = v;
+            if (G > 1 && i == 0 && g > 0) s0[((g - 1) * VC + vc) * L::BUF + (P - 1) + jk] = v;
         }
     }
 }
 
 template <int P, int Q, int G, int NT, int VC, typename T, int NR>
 __device__ __forceinline__ void gather(T *s0, const int32_t (&off)[NR], const T *__restrict__ x, int nvec, int v0,
-                                       int tid)
+                                       int nvalid, int tid)
 {
     T val[NR];
     gather_load<P, G, NT, VC>(val, off, x, nvec, v0, tid);
-    gather_store<P, Q, G, NT, VC>(s0, val, off, nvec, v0, tid);
+    gather_store<P, Q, G, NT, VC>(s0, val, off, nvec, v0, nvalid, tid);
 }
 
-// Transposed restriction: y[node][v0 + vc] += s0 for unmasked nodes.
+// Transposed restriction: y[node][v0 + vc] += element values (both elements'
+// values summed for a face shared inside the group) for unmasked nodes, with
+// hardware atomics (nodes on the group boundary are shared with other groups).
 template <int P, int Q, int G, int NT, int VC, typename T, int NR>
 __device__ __forceinline__ void scatter_add(const T *s0, const int32_t (&off)[NR], T *__restrict__ y, int nvec, int v0,
-                                            int tid)
+                                            int nvalid, int tid)
 {
     static_assert(NR == NodeIO<P, G, NT, VC>::NR, "offset count");
     using L = Lds<Q>;
     using IO = NodeIO<P, G, NT, VC>;
 #pragma unroll
-    for (int r = 0; r < IO::NR; ++r) {
+    for (int r = 0; r < NR; ++r) {
         const int id = tid + r * NT;
         const int vc = id % VC;
-        if (id < IO::NID && off[r] >= 0 && v0 + vc < nvec) {
-            const int gt = id / VC, g = gt / IO::P3, t = gt - g * IO::P3;
-            const int i = t % P, j = (t / P) % P, k = t / (P * P);
-            unsafeAtomicAdd(&y[(int64_t)off[r] * nvec + v0 + vc],
-                            s0[(g * VC + vc) * L::BUF + i + L::PITCH * j + L::PLANE * k]);
+        if (off[r] >= 0 && v0 + vc < nvec) {
+            const int u = id / VC, line = u / IO::W, X = u - line * IO::W;
+            int g, i;
+            line_pos<P, G>(X, nvalid, g, i);
+            const int jk = L::PITCH * (line % P) + L::PLANE * (line / P);
+            T v = s0[(g * VC + vc) * L::BUF + i + jk];
+            if (G > 1 && i == 0 && g > 0) v += s0[((g - 1) * VC + vc) * L::BUF + (P - 1) + jk];
+            unsafeAtomicAdd(&y[(int64_t)off[r] * nvec + v0 + vc], v);
         }
     }
 }
@@ -270,7 +333,7 @@ __device__ __forceinline__ void grad(T *s0, T *s1, T *s2, const T *__restrict__ 
 // ---------------------------------------------------------------------------
 template <int P, int Q, bool COLLOC, int MODE, bool VARK, typename T, int G, int NT, int VC>
 __global__ void __launch_bounds__(NT)
-k_apply(const T *__restrict__ bas, const int64_t nelem, const int nvec, const int32_t *__restrict__ offsets,
+k_apply(const T *__restrict__ bas, const int nex, const int nvec, const int32_t *__restrict__ offsets,
         const T *__restrict__ qdata, const double *__restrict__ kappa, const double *__restrict__ wdet,
         const T *__restrict__ x, T *__restrict__ y)
 {
@@ -284,10 +347,12 @@ k_apply(const T *__restrict__ bas, const int64_t nelem, const int nvec, const in
     T *const s1 = s0 + GV * L::BUF;
     T *const s2 = s1 + GV * L::BUF;
     const int tid = threadIdx.x;
-    const int64_t e0 = xcd_block(blockIdx.x, gridDim.x) * G;
+    const GroupPos gpos = group_pos<G>(xcd_block(blockIdx.x, gridDim.x), nex);
+    const int64_t e0 = gpos.e0;
+    const int nvalid = gpos.nvalid;
 
     int32_t off[NodeIO<P, G, NT, VC>::NR];
-    load_offsets<P, G, NT, VC>(off, offsets, e0, nelem, tid);
+    load_offsets<P, G, NT, VC>(off, offsets, e0, nvalid, tid);
 
     // This lane's geometric factors, loaded once per element group and issued
     // first, so their HBM latency overlaps the gather and the forward
@@ -299,8 +364,8 @@ k_apply(const T *__restrict__ bas, const int64_t nelem, const int nvec, const in
         for (int k = 0; k < RQ; ++k) {
             const int id = tid + k * NT < NPT ? tid + k * NT : NPT - 1;
             const int g = id / Q3, pt = id - g * Q3;
-            // the tail group reads the last element's data (and scatters nothing)
-            const int64_t e = e0 + g < nelem ? e0 + g : nelem - 1;
+            // elements past the end of the row read the first element's data (and scatter nothing)
+            const int64_t e = g < nvalid ? e0 + g : e0;
             const T *qd = qdata + e * (NQD * Q3) + pt;
 #pragma unroll
             for (int m = 0; m < NQD; ++m) qv[k][m] = __builtin_nontemporal_load(&qd[m * Q3]);
@@ -322,13 +387,13 @@ k_apply(const T *__restrict__ bas, const int64_t nelem, const int nvec, const in
                 if (id < NPT) {
                     const int g = id / Q3, pt = id - g * Q3;
                     const int a = pt % Q, b = (pt / Q) % Q, c = pt / Q2;
-                    const int64_t gp = (e0 + g < nelem ? e0 + g : nelem - 1) * Q3 + pt;
+                    const int64_t gp = (g < nvalid ? e0 + g : e0) * Q3 + pt;
                     s0[g * L::BUF + a + L::PITCH * b + L::PLANE * c] = T(wdet[gp] * f[gp]);
                 }
             }
             group_sync<NT>();
         } else {
-            gather<P, Q, G, NT, VC, T>(s0, off, x, nvec, v0, tid);
+            gather<P, Q, G, NT, VC, T>(s0, off, x, nvec, v0, nvalid, tid);
             group_sync<NT>();
             interp<P, Q, COLLOC, GV, NT, T>(s0, bas, tid);
             {
@@ -370,7 +435,7 @@ k_apply(const T *__restrict__ bas, const int64_t nelem, const int nvec, const in
             contract<0, Q, P, P, P, GV, NT, Q, 1>(s0, s0, bas + basis_btf(P, Q), tid);
         }
         group_sync<NT>();
-        scatter_add<P, Q, G, NT, VC, T>(s0, off, y, nvec, v0, tid);
+        scatter_add<P, Q, G, NT, VC, T>(s0, off, y, nvec, v0, nvalid, tid);
         group_sync<NT>();
     }
 }
@@ -386,7 +451,7 @@ k_apply(const T *__restrict__ bas, const int64_t nelem, const int nvec, const in
 // arithmetic per byte to hide that latency otherwise.
 // ---------------------------------------------------------------------------
 template <int Q, int G, int NT, typename T, int RQ>
-__device__ __forceinline__ void load_mass_weights(T (&w)[RQ], const T *__restrict__ qdata, int64_t e0, int64_t nelem,
+__device__ __forceinline__ void load_mass_weights(T (&w)[RQ], const T *__restrict__ qdata, int64_t e0, int nvalid,
                                                   int tid)
 {
     constexpr int Q3 = Q * Q * Q, NPT = G * Q3;
@@ -394,14 +459,14 @@ __device__ __forceinline__ void load_mass_weights(T (&w)[RQ], const T *__restric
     for (int k = 0; k < RQ; ++k) {
         const int id = tid + k * NT < NPT ? tid + k * NT : NPT - 1;
         const int g = id / Q3, pt = id - g * Q3;
-        const int64_t e = e0 + g < nelem ? e0 + g : nelem - 1;  // tail group: the last element's (scatters nothing)
+        const int64_t e = g < nvalid ? e0 + g : e0;  // past the end of the row: the first element's (scatters nothing)
         w[k] = __builtin_nontemporal_load(&qdata[e * Q3 + pt]);
     }
 }
 
 template <int P, int Q, bool COLLOC, typename T, int G, int NT, int VC>
 __global__ void __launch_bounds__(NT)
-k_mass(const T *__restrict__ bas, const int64_t nelem, const int nvec, const int chain,
+k_mass(const T *__restrict__ bas, const int nex, const int64_t ngroups, const int nvec, const int chain,
        const int32_t *__restrict__ offsets, const T *__restrict__ qdata, const T *__restrict__ x, T *__restrict__ y)
 {
     constexpr int Q2 = Q * Q, Q3 = Q2 * Q;
@@ -412,14 +477,14 @@ k_mass(const T *__restrict__ bas, const int64_t nelem, const int nvec, const int
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T *const s0 = reinterpret_cast<T *>(smem_raw);
     const int tid = threadIdx.x;
-    const int64_t ngroups = (nelem + G - 1) / G;
     int64_t grp = xcd_block(blockIdx.x, gridDim.x) * chain;
     const int64_t gend = grp + chain < ngroups ? grp + chain : ngroups;
 
+    GroupPos gpos = group_pos<G>(grp, nex), npos = gpos;
     int32_t off[NR], offn[NR];
-    load_offsets<P, G, NT, VC>(off, offsets, grp * G, nelem, tid);
+    load_offsets<P, G, NT, VC>(off, offsets, gpos.e0, gpos.nvalid, tid);
     T w[RQ], xv[NR];
-    load_mass_weights<Q, G, NT>(w, qdata, grp * G, nelem, tid);
+    load_mass_weights<Q, G, NT>(w, qdata, gpos.e0, gpos.nvalid, tid);
     gather_load<P, G, NT, VC>(xv, off, x, nvec, 0, tid);
 
     for (int v0 = 0;;) {
@@ -431,8 +496,11 @@ k_mass(const T *__restrict__ bas, const int64_t nelem, const int nvec, const int
             ngrp = grp + 1;
         }
         const bool more = ngrp < gend, newgrp = more && ngrp != grp;
-        if (newgrp) load_offsets<P, G, NT, VC>(offn, offsets, ngrp * G, nelem, tid);
-        gather_store<P, Q, G, NT, VC>(s0, xv, off, nvec, v0, tid);
+        if (newgrp) {
+            npos = group_pos<G>(ngrp, nex);
+            load_offsets<P, G, NT, VC>(offn, offsets, npos.e0, npos.nvalid, tid);
+        }
+        gather_store<P, Q, G, NT, VC>(s0, xv, off, nvec, v0, gpos.nvalid, tid);
         group_sync<NT>();
         // the next chunk of the same group needs no new offsets: load it now
         if (more && !newgrp) gather_load<P, G, NT, VC>(xv, off, x, nvec, nv0, tid);
@@ -450,7 +518,7 @@ k_mass(const T *__restrict__ bas, const int64_t nelem, const int nvec, const int
         }
         group_sync<NT>();
         if (newgrp) {
-            load_mass_weights<Q, G, NT>(w, qdata, ngrp * G, nelem, tid);
+            load_mass_weights<Q, G, NT>(w, qdata, npos.e0, npos.nvalid, tid);
             gather_load<P, G, NT, VC>(xv, offn, x, nvec, 0, tid);
         }
         if constexpr (!COLLOC) {
@@ -461,12 +529,13 @@ k_mass(const T *__restrict__ bas, const int64_t nelem, const int nvec, const int
             contract<0, Q, P, P, P, GV, NT, Q, 1>(s0, s0, bas + basis_btf(P, Q), tid);
         }
         group_sync<NT>();
-        scatter_add<P, Q, G, NT, VC, T>(s0, off, y, nvec, v0, tid);
+        scatter_add<P, Q, G, NT, VC, T>(s0, off, y, nvec, v0, gpos.nvalid, tid);
         group_sync<NT>();
         if (!more) break;
         if (newgrp) {
 #pragma unroll
             for (int r = 0; r < NR; ++r) off[r] = offn[r];
+            gpos = npos;
         }
         grp = ngrp;
         v0 = nv0;
@@ -496,9 +565,10 @@ k_kgrad(const double *__restrict__ bas, const int64_t nelem, const int32_t *__re
     const int tid = threadIdx.x;
     const int64_t e0 = xcd_block(blockIdx.x, gridDim.x) * G;
     int32_t off[NodeIO<P, G, NT, 1>::NR];
-    load_offsets<P, G, NT, 1>(off, offsets, e0, nelem, tid);
-    gather<P, Q, G, NT, 1, T>(s0, off, u, 1, 0, tid);
-    gather<P, Q, G, NT, 1, T>(t0, off, r, 1, 0, tid);
+    static_assert(G == 1, "one element per group");
+    load_offsets<P, G, NT, 1>(off, offsets, e0, 1, tid);
+    gather<P, Q, G, NT, 1, T>(s0, off, u, 1, 0, 1, tid);
+    gather<P, Q, G, NT, 1, T>(t0, off, r, 1, 0, 1, tid);
     group_sync<NT>();
     interp<P, Q, COLLOC, G, NT, T>(s0, bas, tid);
     interp<P, Q, COLLOC, G, NT, T>(t0, bas, tid);
@@ -548,17 +618,18 @@ static hipError_t launch_apply_v(const ApplyLaunch &a)
         return hipErrorInvalidValue;
     } else if constexpr (MODE == kMass) {
         const int chain = a.chain > 0 ? a.chain : 1;
-        const int64_t nblk = ((a.v.nelem + G - 1) / G + chain - 1) / chain;
+        const int64_t ngroups = (int64_t)a.v.ney * a.v.nez * ((a.v.nex + G - 1) / G);
+        const int64_t nblk = (ngroups + chain - 1) / chain;
         auto kern = k_mass<P, Q, COLLOC, T, G, NT, VC>;
         hipLaunchKernelGGL(kern, dim3((unsigned)nblk), dim3(NT), lds, a.stream, static_cast<const T *>(a.basis_dev),
-                           a.v.nelem, a.nvec, chain, a.v.offsets, static_cast<const T *>(a.v.qdata),
+                           a.v.nex, ngroups, a.nvec, chain, a.v.offsets, static_cast<const T *>(a.v.qdata),
                            static_cast<const T *>(a.x), static_cast<T *>(a.y));
         return hipGetLastError();
     } else {
-        const int64_t nblk = (a.v.nelem + G - 1) / G;
+        const int64_t nblk = (int64_t)a.v.ney * a.v.nez * ((a.v.nex + G - 1) / G);
         auto kern = k_apply<P, Q, COLLOC, MODE, VARK, T, G, NT, VC>;
         hipLaunchKernelGGL(kern, dim3((unsigned)nblk), dim3(NT), lds, a.stream, static_cast<const T *>(a.basis_dev),
-                           a.v.nelem, a.nvec, a.v.offsets, static_cast<const T *>(a.v.qdata), a.v.kappa, a.wdet,
+                           a.v.nex, a.nvec, a.v.offsets, static_cast<const T *>(a.v.qdata), a.v.kappa, a.wdet,
                            static_cast<const T *>(a.x), static_cast<T *>(a.y));
         return hipGetLastError();
     }

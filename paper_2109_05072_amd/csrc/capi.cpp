@@ -138,18 +138,21 @@ bool valid_variant(const mfhex_op_s &op, int prec, int variant)
 
 int default_variant(const mfhex_op_s &op, int prec, int nvec)
 {
-    // one vector: the measured single-vector best; several: the largest chunk that
-    // fits the LDS budget and does not exceed the vector count
-    if (nvec <= 1) return 0;
+    // one vector: the measured single-vector best for this operator and q;
+    // several: the largest chunk that fits the LDS budget and does not exceed
+    // the vector count
+    if (nvec <= 1) {
+        const int v = (mode_of(op) == kMass ? kDefVariantMass : kDefVariantDiff)[op.Q - 2];
+        return valid_variant(op, prec, v) ? v : 0;
+    }
     for (int v = kNumVariants - 1; v >= 5; --v)
         if (variant_vc(v) <= nvec && valid_variant(op, prec, v)) return v;
     return 0;
 }
 
-// Pipeline depth: the mass kernel chains two element groups per thread group
-// by default (measured fastest on the benchmark meshes); the diffusion kernel
-// takes one.
-int default_chain(const mfhex_op_s &op) { return mode_of(op) == kMass ? 2 : 1; }
+// Pipeline depth: the mass kernel chains the measured best number of element
+// groups per thread group; the diffusion kernel takes one.
+int default_chain(const mfhex_op_s &op) { return mode_of(op) == kMass ? kDefChainMass[op.Q - 2] : 1; }
 
 LaunchCfg config_for(const mfhex_op_s &op, int prec, int nvec)
 {

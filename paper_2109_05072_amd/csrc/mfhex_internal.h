@@ -119,6 +119,14 @@ constexpr size_t apply_lds(int Q, int mode, int elem_bytes, int v)
     return (size_t)variant_g(Q, v, mode) * variant_vc(v) * apply_nbuf(mode) * lds_buf(Q) * elem_bytes;
 }
 constexpr size_t kMaxLds = 65536;
+
+// Single-vector launch defaults per q (index q-2): the variant and, for the
+// mass operator, the pipeline depth measured fastest (median of interleaved
+// timings at about 1e7 DOFs on perturbed box meshes, Gauss q = p+2); orders
+// not measured there keep variant 0.
+constexpr int kDefVariantDiff[9] = {0, 0, 0, 0, 3, 0, 0, 1, 0};
+constexpr int kDefVariantMass[9] = {0, 0, 0, 3, 3, 1, 3, 0, 4};
+constexpr int kDefChainMass[9] = {2, 2, 2, 4, 2, 4, 4, 4, 2};
 // Device basis block (elements): B [Q][P], B^T [P][Q], D [Q][Q], D^T [Q][Q],
 // then the folded (even-odd) forms of the same four matrices: for a matrix M
 // with NO rows and NI columns, row o < ceil(NO/2) holds
