@@ -55,6 +55,8 @@ def lib():
         L.orc_rhs.argtypes = [pp, dp, dp]
         L.orc_kappa_grad.argtypes = [pp, dp, dp, dp]
         L.orc_cg.argtypes = [pp, dp, dp, C.c_int, C.c_double, dp, C.POINTER(C.c_int), C.c_int]
+        L.orc_diagonal.argtypes = [pp, dp]
+        L.orc_pcg.argtypes = [pp, dp, dp, dp, C.c_int, C.c_double, dp, C.POINTER(C.c_int), C.c_int]
         _lib = L
     return _lib
 
@@ -230,6 +232,38 @@ def cg(pr: Problem, b: np.ndarray, maxit: int, rtol: float, nthreads: int = 0):
     code = lib().orc_cg(C.byref(c), _dp(b), _dp(x), maxit, rtol, _dp(hist), C.byref(it), nthreads)
     if code not in (OK, ERR_NOCONV):
         raise RuntimeError(f"oracle cg failed with code {code}")
+    return x, hist[: it.value + 1], it.value, code
+
+
+def diagonal(pr: Problem) -> np.ndarray:
+    """Diagonal of the assembled operator M (sum_e R_e^T A^e R_e) M (0 at masked nodes)."""
+    d = np.zeros(pr.n_nodes)
+    c = pr.cstruct()
+    code = lib().orc_diagonal(C.byref(c), _dp(d))
+    if code != OK:
+        raise RuntimeError(f"oracle diagonal failed with code {code}")
+    return d
+
+
+def jacobi_inverse(d: np.ndarray) -> np.ndarray:
+    """Inverse diagonal for Jacobi preconditioning: 1/d where d > 0, 0 at masked nodes."""
+    out = np.zeros_like(d)
+    pos = d > 0
+    out[pos] = 1.0 / d[pos]
+    return out
+
+
+def pcg(pr: Problem, b: np.ndarray, dinv: np.ndarray, maxit: int, rtol: float, nthreads: int = 0):
+    """Jacobi-preconditioned CG from x0 = 0.  Returns (x, residual-norm history, iters, code)."""
+    b = np.ascontiguousarray(b, dtype=np.float64)
+    dinv = np.ascontiguousarray(dinv, dtype=np.float64)
+    x = np.zeros_like(b)
+    hist = np.zeros(maxit + 1)
+    it = C.c_int(0)
+    c = pr.cstruct()
+    code = lib().orc_pcg(C.byref(c), _dp(b), _dp(dinv), _dp(x), maxit, rtol, _dp(hist), C.byref(it), nthreads)
+    if code not in (OK, ERR_NOCONV):
+        raise RuntimeError(f"oracle pcg failed with code {code}")
     return x, hist[: it.value + 1], it.value, code
 
 

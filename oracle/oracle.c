@@ -637,3 +637,103 @@ int orc_cg(const orc_prob *pr, const double *b, double *x, int maxit, double rto
     free(r); free(p); free(Ap);
     return status;
 }
+
+/* ------------------------------------------------------------------------- */
+/* Operator diagonal and Jacobi-preconditioned CG                            */
+/* ------------------------------------------------------------------------- */
+
+/* d = diag( M (sum_e R_e^T A^e R_e) M ): every element adds the diagonal of
+ * its element matrix at its nodes, masked nodes stay 0.  The element
+ * diagonal comes straight from the dense tabulation:
+ *     (A^e)_nn = sum_pt kappa dphi_n(pt)^T D(pt) dphi_n(pt)   (diffusion),
+ *     (A^e)_nn = sum_pt w detJ phi_n(pt)^2                     (mass).
+ * Elements are visited in order, so the sums are deterministic. */
+int orc_diagonal(const orc_prob *pr, double *d)
+{
+    if (check_prob(pr) || !d) return ORC_ERR_ARG;
+    orc_tab t;
+    if (tab_build(pr, &t)) return ORC_ERR_MEM;
+    const int P3 = t.P3, Q3 = t.Q3;
+    const size_t S = (size_t)Q3 * P3;
+    const int64_t N = n_nodes(pr), E = (int64_t)pr->nex * pr->ney * pr->nez;
+    int64_t *gid = malloc(sizeof(int64_t) * P3);
+    double *de = malloc(sizeof(double) * P3);
+    if (!gid || !de) { free(gid); free(de); tab_free(&t); return ORC_ERR_MEM; }
+    for (int64_t i = 0; i < N; ++i) d[i] = 0.0;
+    for (int64_t e = 0; e < E; ++e) {
+        double X[8][3];
+        elem_vertices(pr, e, X);
+        elem_nodes(pr, e, pr->dirichlet, gid);
+        for (int n = 0; n < P3; ++n) de[n] = 0.0;
+        for (int pt = 0; pt < Q3; ++pt) {
+            double wdet, D[3][3];
+            point_data(&t, X, pt, &wdet, D);
+            double kap = pr->kappa ? pr->kappa[e * Q3 + pt] : 1.0;
+            for (int n = 0; n < P3; ++n) {
+                size_t on = (size_t)pt * P3 + n;
+                if (pr->kind == ORC_MASS) {
+                    de[n] += wdet * t.phi[on] * t.phi[on];
+                } else {
+                    double g[3] = {t.dphi[on], t.dphi[S + on], t.dphi[2 * S + on]};
+                    double s = 0.0;
+                    for (int a = 0; a < 3; ++a)
+                        for (int b = 0; b < 3; ++b) s += g[a] * D[a][b] * g[b];
+                    de[n] += kap * s;
+                }
+            }
+        }
+        for (int n = 0; n < P3; ++n)
+            if (gid[n] >= 0) d[gid[n]] += de[n];
+    }
+    free(gid); free(de); tab_free(&t);
+    return ORC_OK;
+}
+
+/* Jacobi-preconditioned CG in textbook form, x0 = 0:
+ *     z = Dinv r,  alpha = r.z / p.Ap,  x += alpha p,  r -= alpha Ap,
+ *     z = Dinv r,  beta = (r.z)_new / (r.z)_old,  p = z + beta p,
+ * stopping on the unpreconditioned residual ||r|| <= rtol ||b|| exactly like
+ * orc_cg; rhist[k] = ||r_k||.  dinv: inverse of the operator diagonal (0 at
+ * masked nodes).  Sec. 1 pairs CG with preconditioners on top of
+ * sum-factorized operator evaluation; Jacobi (diagonal) scaling is the
+ * smoother the Nek5000/RS solvers of Sec. 2 accelerate with Chebyshev. */
+int orc_pcg(const orc_prob *pr, const double *b, const double *dinv, double *x, int maxit, double rtol,
+            double *rhist, int *iters, int nthreads)
+{
+    if (check_prob(pr) || maxit < 0 || !dinv) return ORC_ERR_ARG;
+    const int64_t N = n_nodes(pr);
+    double *r = malloc(sizeof(double) * N), *z = malloc(sizeof(double) * N);
+    double *p = malloc(sizeof(double) * N), *Ap = malloc(sizeof(double) * N);
+    if (!r || !z || !p || !Ap) { free(r); free(z); free(p); free(Ap); return ORC_ERR_MEM; }
+    for (int64_t i = 0; i < N; ++i) {
+        x[i] = 0.0;
+        r[i] = b[i];
+        z[i] = dinv[i] * r[i];
+        p[i] = z[i];
+    }
+    double rz = dot(N, r, z), bn = sqrt(dot(N, r, r));
+    if (rhist) rhist[0] = bn;
+    int k = 0, status = ORC_OK;
+    if (bn == 0.0) { *iters = 0; free(r); free(z); free(p); free(Ap); return ORC_OK; }
+    status = ORC_ERR_NOCONV;
+    while (k < maxit) {
+        int e = orc_apply(pr, 1, p, Ap, nthreads);
+        if (e) { status = e; break; }
+        double pAp = dot(N, p, Ap);
+        if (!(pAp > 0.0)) { status = ORC_ERR_BREAKDOWN; break; }
+        double alpha = rz / pAp;
+        for (int64_t i = 0; i < N; ++i) { x[i] += alpha * p[i]; r[i] -= alpha * Ap[i]; }
+        double rn = sqrt(dot(N, r, r));
+        ++k;
+        if (rhist) rhist[k] = rn;
+        if (rn <= rtol * bn) { status = ORC_OK; break; }
+        for (int64_t i = 0; i < N; ++i) z[i] = dinv[i] * r[i];
+        double rz_new = dot(N, r, z);
+        double beta = rz_new / rz;
+        for (int64_t i = 0; i < N; ++i) p[i] = z[i] + beta * p[i];
+        rz = rz_new;
+    }
+    *iters = k;
+    free(r); free(z); free(p); free(Ap);
+    return status;
+}

@@ -343,3 +343,63 @@ def test_kappa_gradient_central_differences_are_exact():
         d[e, q] = 1.0
         fd = (loss(kap + 0.5 * d) - loss(kap - 0.5 * d)) / 1.0
         assert abs(fd - g[e, q]) <= 1e-9 * max(1.0, abs(g[e, q]))
+
+
+# --- operator diagonal and Jacobi-preconditioned CG ---------------------------------------
+
+@pytest.mark.parametrize("kind,quad,dirichlet,with_kappa", [
+    (oracle.DIFFUSION, oracle.GAUSS, 1, False), (oracle.DIFFUSION, oracle.GAUSS, 0, True),
+    (oracle.DIFFUSION, oracle.GLL, 1, False), (oracle.MASS, oracle.GAUSS, 0, False)])
+def test_diagonal_is_the_diagonal_of_the_applied_identity(kind, quad, dirichlet, with_kappa):
+    # A e_i for every unit vector e_i (the apply on the identity, one column per node) gives
+    # the dense matrix; its diagonal must be what orc_diagonal accumulates element by element
+    kappa = None
+    if with_kappa:
+        pr0 = _prob(2, 2, kind, quad, dirichlet=dirichlet)
+        xq, _ = oracle.qpoint_geometry(pr0)
+        kappa = synth.kappa_field(xq.reshape(-1, 3)).reshape(pr0.n_elem, -1)
+    pr = _prob(2, 2, kind, quad, dirichlet=dirichlet, kappa=kappa)
+    A = oracle.apply(pr, np.eye(pr.n_nodes))
+    d = oracle.diagonal(pr)
+    np.testing.assert_allclose(d, np.diag(A), rtol=1e-13, atol=1e-15 * np.abs(d).max())
+    if dirichlet:
+        assert np.all(d[~_interior(pr)] == 0.0) and np.all(d[_interior(pr)] > 0.0)
+
+
+def test_pcg_matches_direct_solve():
+    pr = _prob(3, 2, oracle.DIFFUSION, dirichlet=1)
+    inner = _interior(pr)
+    b = synth.uniform_vector(pr.n_nodes) * inner
+    dinv = oracle.jacobi_inverse(oracle.diagonal(pr))
+    x, hist, it, code = oracle.pcg(pr, b, dinv, maxit=1000, rtol=1e-13)
+    assert code == oracle.OK
+    xs = spla.spsolve(oracle.assemble(pr)[inner][:, inner], b[inner])
+    assert np.abs(x[inner] - xs).max() < 1e-10 * np.abs(xs).max()
+    assert np.all(x[~inner] == 0.0)
+
+
+def test_pcg_with_identity_scaling_is_cg():
+    # Dinv = 1 on the unmasked nodes (0 on masked ones, where r is 0 anyway) makes z = r, so
+    # r.z = r.r and every iterate equals plain CG's: the histories agree to the last bit
+    pr = _prob(3, 3, oracle.DIFFUSION, dirichlet=1)
+    inner = _interior(pr)
+    b = synth.uniform_vector(pr.n_nodes) * inner
+    _, h_cg, it_cg, _ = oracle.cg(pr, b, maxit=60, rtol=0.0)
+    _, h_pcg, it_pcg, _ = oracle.pcg(pr, b, inner.astype(np.float64), maxit=60, rtol=0.0)
+    assert it_cg == it_pcg == 60
+    assert np.array_equal(h_cg, h_pcg)
+
+
+def test_jacobi_cuts_iterations_for_a_high_contrast_coefficient():
+    # kappa varying over four orders of magnitude across the mesh: diagonal scaling removes the
+    # coefficient scale from the spectrum, so PCG needs far fewer iterations than CG
+    pr0 = _prob(4, 2, oracle.DIFFUSION, dirichlet=1)
+    xq, _ = oracle.qpoint_geometry(pr0)
+    xyz = xq.reshape(pr0.n_elem, -1, 3)
+    kappa = 10.0 ** (4.0 * xyz[:, :, 0])
+    pr = _prob(4, 2, oracle.DIFFUSION, dirichlet=1, kappa=kappa)
+    b = synth.uniform_vector(pr.n_nodes) * _interior(pr)
+    _, _, it_cg, c1 = oracle.cg(pr, b, maxit=5000, rtol=1e-10)
+    _, _, it_pcg, c2 = oracle.pcg(pr, b, oracle.jacobi_inverse(oracle.diagonal(pr)), maxit=5000, rtol=1e-10)
+    assert c1 == oracle.OK and c2 == oracle.OK
+    assert it_pcg < 0.5 * it_cg
