@@ -59,6 +59,7 @@ enum { MFHEX_MASS = 1, MFHEX_DIFFUSION = 2 };      /* operator kind       */
 enum { MFHEX_GAUSS = 0, MFHEX_GLL = 1 };           /* quadrature rule     */
 enum { MFHEX_F64 = 0, MFHEX_F32 = 1 };             /* arithmetic / data   */
 enum { MFHEX_CG_F64 = 0, MFHEX_CG_MIXED = 1 };     /* solver mode         */
+enum { MFHEX_PRECOND_NONE = 0, MFHEX_PRECOND_JACOBI = 1 }; /* CG preconditioner */
 
 /* desc.flags bits */
 #define MFHEX_FLAG_F32 1u  /* also build FP32 quadrature data (for prec = MFHEX_F32) */
@@ -134,6 +135,16 @@ int mfhex_apply_adjoint(mfhex_op op, int prec, int nrhs, const void *x_dev, void
  * For a loss L(y), r = dL/dy gives dL/dkappa.  Asynchronous. */
 int mfhex_kappa_grad(mfhex_op op, const double *u_dev, const double *r_dev, double *g_dev, void *stream);
 
+/* Diagonal of the assembled operator M (sum_e R_e^T A^e R_e) M, device FP64
+ * [n_nodes], overwritten (0 at masked nodes; with ncomp = 3 it is the
+ * diagonal of each component's block).  Evaluated matrix-free: each
+ * element's diagonal is a sum of transposed interpolations of its point
+ * factors with squared or mixed 1D matrices (the sum factorization of
+ * Sec. 1 and the operator form A^e = Dhat^T G^e Dhat of Sec. 2), added with
+ * atomics.  The Jacobi preconditioner of mfhex_cg uses it.  Variable
+ * coefficient operators need mfhex_set_kappa first.  Asynchronous. */
+int mfhex_diagonal(mfhex_op op, double *diag_dev, void *stream);
+
 /* Physical coordinates of the quadrature points, device FP64
  * [n_elem][q^3][3], and of the nodes, device FP64 [n_nodes][3] (for
  * evaluating coefficients, forcings and nodal fields).  Asynchronous. */
@@ -157,9 +168,13 @@ int mfhex_rhs(mfhex_op op, const double *f_dev, double *b_dev, void *stream);
  *   residual.  maxit bounds the iterations.  check_every: iterations
  *   between host convergence checks (one stream sync each).  x0_is_zero = 0
  *   starts from the given x.  max_iters_exact = 1 runs exactly maxit
- *   iterations without convergence checks (FP64 mode; returns MFHEX_OK). */
+ *   iterations without convergence checks (FP64 mode; returns MFHEX_OK).
+ *   precond MFHEX_PRECOND_JACOBI: Jacobi-preconditioned CG in either mode,
+ *   z = D^-1 r with D = mfhex_diagonal (computed and inverted at the start of
+ *   every solve; 0 at masked nodes), alpha = r.z / p.Ap, beta from r.z; the
+ *   stopping test stays on ||r||.  pad_ must be 0. */
 typedef struct {
-    int32_t maxit, check_every, mode, replace_every, x0_is_zero, max_iters_exact;
+    int32_t maxit, check_every, mode, replace_every, x0_is_zero, max_iters_exact, precond, pad_;
     double rtol, replace_delta;
 } mfhex_cg_opts;
 
@@ -177,7 +192,8 @@ typedef struct {
  * `stream`.  Returns MFHEX_OK on convergence, MFHEX_ERR_NOCONV at maxit,
  * MFHEX_ERR_BREAKDOWN on p^T A p <= 0 / non-finite values.  (Sec. 1: CG
  * on the sum-factorized operator; Sec. 2: the benchmarks run it
- * unpreconditioned.) */
+ * unpreconditioned; Jacobi scaling is the smoother of the Nek5000/RS
+ * solvers of Sec. 2.) */
 int mfhex_cg(mfhex_op op, const double *b_dev, double *x_dev, void *cg_work_dev, const mfhex_cg_opts *opts,
              mfhex_cg_stats *stats, double *rhist, void *stream);
 

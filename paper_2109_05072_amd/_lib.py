@@ -25,13 +25,14 @@ MFHEX_MASS, MFHEX_DIFFUSION = 1, 2
 MFHEX_GAUSS, MFHEX_GLL = 0, 1
 MFHEX_F64, MFHEX_F32 = 0, 1
 MFHEX_CG_F64, MFHEX_CG_MIXED = 0, 1
+MFHEX_PRECOND_NONE, MFHEX_PRECOND_JACOBI = 0, 1
 MFHEX_FLAG_F32, MFHEX_FLAG_RHS = 1, 2
 
 # every symbol include/mfhex.h declares
 EXPORTS = (
     "mfhex_query", "mfhex_create", "mfhex_destroy", "mfhex_set_kappa", "mfhex_apply", "mfhex_apply_add",
     "mfhex_apply_adjoint", "mfhex_kappa_grad", "mfhex_qpoint_coords", "mfhex_node_coords", "mfhex_rhs",
-    "mfhex_cg", "mfhex_tune", "mfhex_get_config", "mfhex_set_config", "mfhex_strerror", "mfhex_last_error",
+    "mfhex_cg", "mfhex_tune", "mfhex_get_config", "mfhex_set_config", "mfhex_diagonal", "mfhex_strerror", "mfhex_last_error",
     "mfhex_basis_1d", "mfhex_version",
 )
 
@@ -56,7 +57,7 @@ class mfhex_sizes(C.Structure):
 class mfhex_cg_opts(C.Structure):
     _fields_ = [("maxit", C.c_int32), ("check_every", C.c_int32), ("mode", C.c_int32),
                 ("replace_every", C.c_int32), ("x0_is_zero", C.c_int32), ("max_iters_exact", C.c_int32),
-                ("rtol", C.c_double), ("replace_delta", C.c_double)]
+                ("precond", C.c_int32), ("pad_", C.c_int32), ("rtol", C.c_double), ("replace_delta", C.c_double)]
 
 
 class mfhex_cg_stats(C.Structure):
@@ -103,6 +104,7 @@ def load(path: str = LIB_PATH):
         "mfhex_tune": ([vp, i32, i32, vp, C.c_char_p, vp], i32),
         "mfhex_get_config": ([vp, i32, i32, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                               C.POINTER(C.c_int32), C.POINTER(C.c_int32)], i32),
+        "mfhex_diagonal": ([vp, vp, vp], i32),
         "mfhex_set_config": ([vp, i32, i32, C.c_int32, C.c_int32], i32),
         "mfhex_strerror": ([i32], C.c_char_p),
         "mfhex_last_error": ([vp], C.c_char_p),
@@ -198,6 +200,10 @@ def mfhex_get_config(op: int, prec: int, nrhs: int):
 
 def mfhex_set_config(op: int, prec: int, nrhs: int, variant: int, groups_per_block: int = 0) -> None:
     check(load().mfhex_set_config(op, prec, nrhs, variant, groups_per_block), op)
+
+
+def mfhex_diagonal(op: int, d: int, stream: int) -> None:
+    check(load().mfhex_diagonal(op, d, stream), op)
 
 
 def mfhex_strerror(code: int) -> str:

@@ -32,6 +32,7 @@
 // interpolate back.
 #pragma once
 
+#include "diag_kernels.hpp"
 #include "mfhex_internal.h"
 
 namespace mfhex {
@@ -693,5 +694,10 @@ static hipError_t launch_kgrad_pq(const KgradLaunch &a)
     {                                                                                                  \
         if (a.colloc) return launch_kgrad_pq<N + 1, N + 1, true>(a);                                   \
         return launch_kgrad_pq<N + 1, N + 2, false>(a);                                                \
+    }                                                                                                  \
+    hipError_t launch_diag_p##N(const DiagLaunch &a)                                                   \
+    {                                                                                                  \
+        if (a.colloc) return launch_diag_pq<N + 1, N + 1>(a);                                          \
+        return launch_diag_pq<N + 1, N + 2>(a);                                                        \
     }                                                                                                  \
     }

@@ -20,19 +20,33 @@ enum : int {
     kScFlag = 7,    // 1 after a breakdown / non-finite value
     kScTmp = 8,
     kScRRPrev = 9,  // r.r before the last beta update
+    kScRZ = 10,     // r.z of the current residual (Jacobi-preconditioned CG)
+    kScRZPrev = 11, // r.z before the last beta update
+    kScRZTmp = 12,
     kNumSc = 16
 };
-enum : int { kFinStore = 0, kFinAlpha = 1, kFinBeta = 2 };
+enum : int { kFinStore = 0, kFinAlpha = 1, kFinBeta = 2, kFinAlphaPre = 3, kFinBetaPre = 4 };
 
 // prec arguments are MFHEX_F64 / MFHEX_F32.
 hipError_t launch_dot(const void *a, int pa, const void *b, int pb, int64_t n, double *partial, hipStream_t s);
 // kFinStore: sc[k] = sum; kFinAlpha: pAp, alpha = rr / pAp (flag on pAp <= 0);
 // kFinBeta: rr_new, beta = rr_new / rr, rr = rr_new, hist[k] = sqrt(rr_new).
+// Preconditioned forms: kFinAlphaPre: alpha = rz / pAp; kFinBetaPre: the
+// partials hold r.r then r.z (2 kRedBlocks): rr = rr_new, beta = rz_new / rz,
+// rz = rz_new, hist[k] = sqrt(rr_new).
 hipError_t launch_finalize(const double *partial, double *sc, int op, int k, double *hist, int hist_len,
                            hipStream_t s);
 hipError_t launch_update_xr(double *x, void *r, const void *p, const void *Ap, int prec, const double *sc, int64_t n,
                             double *partial, hipStream_t s);
 hipError_t launch_update_p(const void *r, void *p, int prec, const double *sc, int64_t n, hipStream_t s);
+// x += alpha p; r -= alpha Ap; z = dinv r; partials of r.r and r.z (2 kRedBlocks).
+hipError_t launch_update_xrz(double *x, void *r, const void *p, const void *Ap, const void *dinv, void *z, int prec,
+                             const double *sc, int64_t n, double *partial, hipStream_t s);
+// z = dinv r; partials of r.z (kRedBlocks).
+hipError_t launch_precond(const void *r, const void *dinv, void *z, int prec, int64_t n, double *partial,
+                          hipStream_t s);
+// dinv64 = 1 / d where d > 0, else 0 (masked nodes); dinv32 = fp32(dinv64).
+hipError_t launch_jacobi_inverse(const double *d, double *dinv64, float *dinv32, int64_t n, hipStream_t s);
 hipError_t launch_residual(const double *b, const double *Ax, double *r64, float *r32, int64_t n, double *partial,
                            hipStream_t s);
 hipError_t launch_copy(const void *src, int ps, void *dst, int pd, int64_t n, hipStream_t s);

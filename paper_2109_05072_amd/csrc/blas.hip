@@ -77,7 +77,42 @@ __global__ void __launch_bounds__(kRedThreads) k_finalize(const double *__restri
         sc[kScRR] = s;
         if (!isfinite(s)) sc[kScFlag] = 1.0;
         if (hist && k >= 0 && k < hist_len) hist[k] = sqrt(s);
+    } else if (op == kFinAlphaPre) {
+        sc[kScPAp] = s;
+        const double al = sc[kScRZ] / s;
+        if (!(s > 0.0) || !isfinite(al)) {
+            sc[kScFlag] = 1.0;
+            sc[kScAlpha] = 0.0;
+        } else {
+            sc[kScAlpha] = al;
+        }
     }
+}
+
+// Preconditioned beta step: partial[0..) holds r.r, partial[kRedBlocks..) holds r.z.
+__global__ void __launch_bounds__(kRedThreads) k_finalize_beta_pre(const double *__restrict__ partial,
+                                                                   double *__restrict__ sc, int k,
+                                                                   double *__restrict__ hist, int hist_len)
+{
+    __shared__ double sh[kRedThreads];
+    double a = 0.0, b = 0.0;
+    for (int i = threadIdx.x; i < kRedBlocks; i += kRedThreads) {
+        a += partial[i];
+        b += partial[kRedBlocks + i];
+    }
+    a = block_sum(a, sh);
+    __syncthreads();
+    b = block_sum(b, sh);
+    if (threadIdx.x != 0) return;
+    const double rz = sc[kScRZ];
+    sc[kScRRPrev] = sc[kScRR];
+    sc[kScRRNew] = a;
+    sc[kScRR] = a;
+    sc[kScRZPrev] = rz;
+    sc[kScBeta] = (rz > 0.0) ? b / rz : 0.0;
+    sc[kScRZ] = b;
+    if (!isfinite(a) || !isfinite(b)) sc[kScFlag] = 1.0;
+    if (hist && k >= 0 && k < hist_len) hist[k] = sqrt(a);
 }
 
 // x += alpha p; r -= alpha Ap; partial sums of r.r.  x is FP64; r, p, Ap in T.
@@ -98,6 +133,61 @@ __global__ void __launch_bounds__(kRedThreads) k_update_xr(double *__restrict__ 
     }
     s = block_sum(s, sh);
     if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+// x += alpha p; r -= alpha Ap; z = dinv r; partial sums of r.r and r.z.
+template <typename T>
+__global__ void __launch_bounds__(kRedThreads) k_update_xrz(double *__restrict__ x, T *__restrict__ r,
+                                                            const T *__restrict__ p, const T *__restrict__ Ap,
+                                                            const T *__restrict__ dinv, T *__restrict__ z,
+                                                            const double *__restrict__ sc, int64_t n,
+                                                            double *__restrict__ partial)
+{
+    __shared__ double sh[kRedThreads];
+    const double al = sc[kScAlpha];
+    double srr = 0.0, srz = 0.0;
+    for (int64_t i = blockIdx.x * (int64_t)kRedThreads + threadIdx.x; i < n; i += (int64_t)kRedBlocks * kRedThreads) {
+        x[i] += al * (double)p[i];
+        const T ri = (T)((double)r[i] - al * (double)Ap[i]);
+        const T zi = (T)((double)dinv[i] * (double)ri);
+        r[i] = ri;
+        z[i] = zi;
+        srr += (double)ri * (double)ri;
+        srz += (double)ri * (double)zi;
+    }
+    srr = block_sum(srr, sh);
+    __syncthreads();
+    srz = block_sum(srz, sh);
+    if (threadIdx.x == 0) {
+        partial[blockIdx.x] = srr;
+        partial[kRedBlocks + blockIdx.x] = srz;
+    }
+}
+
+// z = dinv r; partial sums of r.z.
+template <typename T>
+__global__ void __launch_bounds__(kRedThreads) k_precond(const T *__restrict__ r, const T *__restrict__ dinv,
+                                                         T *__restrict__ z, int64_t n, double *__restrict__ partial)
+{
+    __shared__ double sh[kRedThreads];
+    double s = 0.0;
+    for (int64_t i = blockIdx.x * (int64_t)kRedThreads + threadIdx.x; i < n; i += (int64_t)kRedBlocks * kRedThreads) {
+        const T zi = (T)((double)dinv[i] * (double)r[i]);
+        z[i] = zi;
+        s += (double)r[i] * (double)zi;
+    }
+    s = block_sum(s, sh);
+    if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+__global__ void k_jacobi_inverse(const double *__restrict__ d, double *__restrict__ dinv64, float *__restrict__ dinv32,
+                                 int64_t n)
+{
+    for (int64_t i = blockIdx.x * (int64_t)kRedThreads + threadIdx.x; i < n; i += (int64_t)kRedBlocks * kRedThreads) {
+        const double v = d[i] > 0.0 ? 1.0 / d[i] : 0.0;
+        dinv64[i] = v;
+        if (dinv32) dinv32[i] = (float)v;
+    }
 }
 
 template <typename T>
@@ -206,7 +296,38 @@ hipError_t launch_dot(const void *a, int pa, const void *b, int pb, int64_t n, d
 hipError_t launch_finalize(const double *partial, double *sc, int op, int k, double *hist, int hist_len,
                            hipStream_t s)
 {
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kRedThreads), 0, s, partial, sc, op, k, hist, hist_len);
+    if (op == kFinBetaPre)
+        hipLaunchKernelGGL(k_finalize_beta_pre, dim3(1), dim3(kRedThreads), 0, s, partial, sc, k, hist, hist_len);
+    else
+        hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kRedThreads), 0, s, partial, sc, op, k, hist, hist_len);
+    return hipGetLastError();
+}
+
+hipError_t launch_update_xrz(double *x, void *r, const void *p, const void *Ap, const void *dinv, void *z, int prec,
+                             const double *sc, int64_t n, double *partial, hipStream_t s)
+{
+    if (prec == MFHEX_F64)
+        hipLaunchKernelGGL(k_update_xrz<double>, GRID, x, (double *)r, (const double *)p, (const double *)Ap,
+                           (const double *)dinv, (double *)z, sc, n, partial);
+    else
+        hipLaunchKernelGGL(k_update_xrz<float>, GRID, x, (float *)r, (const float *)p, (const float *)Ap,
+                           (const float *)dinv, (float *)z, sc, n, partial);
+    return hipGetLastError();
+}
+
+hipError_t launch_precond(const void *r, const void *dinv, void *z, int prec, int64_t n, double *partial,
+                          hipStream_t s)
+{
+    if (prec == MFHEX_F64)
+        hipLaunchKernelGGL(k_precond<double>, GRID, (const double *)r, (const double *)dinv, (double *)z, n, partial);
+    else
+        hipLaunchKernelGGL(k_precond<float>, GRID, (const float *)r, (const float *)dinv, (float *)z, n, partial);
+    return hipGetLastError();
+}
+
+hipError_t launch_jacobi_inverse(const double *d, double *dinv64, float *dinv32, int64_t n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_jacobi_inverse, GRID, d, dinv64, dinv32, n);
     return hipGetLastError();
 }
 

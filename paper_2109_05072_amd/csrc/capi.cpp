@@ -110,6 +110,14 @@ CgLayout cg_layout(int64_t n)
     o += al(kNumSc * 8);
     L.hist = o;
     o += al(kHist * 8);
+    L.z64 = o;
+    o += al(n * 8);
+    L.dinv64 = o;
+    o += al(n * 8);
+    L.z32 = o;
+    o += al(n * 4);
+    L.dinv32 = o;
+    o += al(n * 4);
     L.total = o;
     return L;
 }
@@ -194,6 +202,21 @@ hipError_t launch_kgrad(const KgradLaunch &a)
     }
 }
 
+hipError_t launch_diag(const DiagLaunch &a)
+{
+    switch (a.P - 1) {
+    case 1: return launch_diag_p1(a);
+    case 2: return launch_diag_p2(a);
+    case 3: return launch_diag_p3(a);
+    case 4: return launch_diag_p4(a);
+    case 5: return launch_diag_p5(a);
+    case 6: return launch_diag_p6(a);
+    case 7: return launch_diag_p7(a);
+    case 8: return launch_diag_p8(a);
+    default: return hipErrorInvalidValue;
+    }
+}
+
 static OpView view_of(const mfhex_op_s &op, int prec)
 {
     OpView v;
@@ -251,6 +274,25 @@ int apply_impl(mfhex_op op, int prec, int nrhs, const void *x, void *y, hipStrea
     a.wdet = nullptr;
     a.stream = s;
     return check_hip(op, launch_apply(a), "apply kernel launch");
+}
+
+int diagonal_impl(mfhex_op op, double *d, hipStream_t s)
+{
+    if (!op) return set_error(nullptr, MFHEX_ERR_ARG, "null handle");
+    if (!d) return set_error(op, MFHEX_ERR_ARG, "null output");
+    if (op->d.variable_kappa && !op->kappa_set) return set_error(op, MFHEX_ERR_STATE, "kappa not set");
+    int c = check_hip(op, hipMemsetAsync(d, 0, op->N * sizeof(double), s), "hipMemsetAsync");
+    if (c) return c;
+    DiagLaunch a{};
+    a.v = view_of(*op, MFHEX_F64);
+    a.P = op->P;
+    a.colloc = op->basis.colloc;
+    a.mode = mode_of(*op);
+    a.vark = op->d.variable_kappa;
+    a.basis_dev = op->basis64;
+    a.d = d;
+    a.stream = s;
+    return check_hip(op, launch_diag(a), "diagonal kernel launch");
 }
 
 }  // namespace mfhex
@@ -433,6 +475,11 @@ int mfhex_kappa_grad(mfhex_op op, const double *u_dev, const double *r_dev, doub
     a.g = g_dev;
     a.stream = static_cast<hipStream_t>(stream);
     return check_hip(op, launch_kgrad(a), "coefficient gradient kernel launch");
+}
+
+int mfhex_diagonal(mfhex_op op, double *diag_dev, void *stream)
+{
+    return diagonal_impl(op, diag_dev, static_cast<hipStream_t>(stream));
 }
 
 int mfhex_qpoint_coords(mfhex_op op, double *xyz_dev, void *stream)

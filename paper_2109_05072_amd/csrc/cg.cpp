@@ -17,6 +17,14 @@
 // residual r = fp32(b - A64 x) and beta is recomputed from it; convergence is
 // only accepted on that true residual.  If three replacements in a row fail
 // to lower the true residual, the solve continues in FP64.
+//
+// Jacobi preconditioning (either mode): z = D^-1 r with D the operator
+// diagonal (mfhex_diagonal, inverted once per solve; 0 at masked nodes),
+// alpha = r.z / p.Ap, beta = (r.z)_new / (r.z)_old, p = z + beta p; the
+// update kernel forms z and both r.r and r.z in the same pass, and every
+// residual replacement recomputes z and r.z.  Convergence is still measured
+// on ||r||.  (Sec. 1: CG with preconditioners on sum-factorized operators;
+// Sec. 2, Nek5000/RS: Jacobi smoothing.)
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -34,6 +42,9 @@ struct Ctx {
     int64_t n;
     double *r64, *p64, *ap64, *partial, *sc, *hist;
     float *r32, *p32, *ap32;
+    bool pre;  // Jacobi preconditioning
+    double *z64, *dinv64;
+    float *z32, *dinv32;
 };
 
 #define TRY(expr)                         \
@@ -54,6 +65,15 @@ int read_scalars(Ctx &ctx)
 int dot_store(Ctx &ctx, const void *a, int pa, const void *b, int pb, int slot)
 {
     HIP(launch_dot(a, pa, b, pb, ctx.n, ctx.partial, ctx.s), "dot kernel");
+    HIP(launch_finalize(ctx.partial, ctx.sc, kFinStore, slot, nullptr, 0, ctx.s), "finalize kernel");
+    return MFHEX_OK;
+}
+
+// z = dinv r and r.z into sc[slot] (prec: of r, z and dinv).
+int precond_store(Ctx &ctx, int prec, const void *r, void *z, int slot)
+{
+    const void *dinv = prec == MFHEX_F64 ? (const void *)ctx.dinv64 : (const void *)ctx.dinv32;
+    HIP(launch_precond(r, dinv, z, prec, ctx.n, ctx.partial, ctx.s), "preconditioner kernel");
     HIP(launch_finalize(ctx.partial, ctx.sc, kFinStore, slot, nullptr, 0, ctx.s), "finalize kernel");
     return MFHEX_OK;
 }
@@ -80,7 +100,9 @@ int cg64(Ctx &ctx, const double *b, double *x, const mfhex_cg_opts &o, bool x0_z
         TRY(true_residual(ctx, b, x, ctx.r64, nullptr));
         HIP(launch_finalize(ctx.partial, ctx.sc, kFinStore, kScRR, nullptr, 0, ctx.s), "finalize kernel");
     }
-    HIP(launch_copy(ctx.r64, MFHEX_F64, ctx.p64, MFHEX_F64, n, ctx.s), "copy kernel");
+    if (ctx.pre) TRY(precond_store(ctx, MFHEX_F64, ctx.r64, ctx.z64, kScRZ));
+    double *const zr = ctx.pre ? ctx.z64 : ctx.r64;  // search directions come from z (= r unpreconditioned)
+    HIP(launch_copy(zr, MFHEX_F64, ctx.p64, MFHEX_F64, n, ctx.s), "copy kernel");
     const bool exact = o.max_iters_exact != 0;
     const int every = std::max(1, o.check_every);
     int k = k0;
@@ -88,10 +110,18 @@ int cg64(Ctx &ctx, const double *b, double *x, const mfhex_cg_opts &o, bool x0_z
     while (k < o.maxit) {
         TRY(apply_impl(ctx.op, MFHEX_F64, 1, ctx.p64, ctx.ap64, ctx.s, true, -1));
         HIP(launch_dot(ctx.p64, MFHEX_F64, ctx.ap64, MFHEX_F64, n, ctx.partial, ctx.s), "dot kernel");
-        HIP(launch_finalize(ctx.partial, ctx.sc, kFinAlpha, 0, nullptr, 0, ctx.s), "finalize kernel");
-        HIP(launch_update_xr(x, ctx.r64, ctx.p64, ctx.ap64, MFHEX_F64, ctx.sc, n, ctx.partial, ctx.s), "update kernel");
+        HIP(launch_finalize(ctx.partial, ctx.sc, ctx.pre ? kFinAlphaPre : kFinAlpha, 0, nullptr, 0, ctx.s),
+            "finalize kernel");
+        if (ctx.pre)
+            HIP(launch_update_xrz(x, ctx.r64, ctx.p64, ctx.ap64, ctx.dinv64, ctx.z64, MFHEX_F64, ctx.sc, n, ctx.partial,
+                                  ctx.s),
+                "update kernel");
+        else
+            HIP(launch_update_xr(x, ctx.r64, ctx.p64, ctx.ap64, MFHEX_F64, ctx.sc, n, ctx.partial, ctx.s),
+                "update kernel");
         ++k;
-        HIP(launch_finalize(ctx.partial, ctx.sc, kFinBeta, k, ctx.hist, kHist, ctx.s), "finalize kernel");
+        HIP(launch_finalize(ctx.partial, ctx.sc, ctx.pre ? kFinBetaPre : kFinBeta, k, ctx.hist, kHist, ctx.s),
+            "finalize kernel");
         if (!exact && (k % every == 0 || k == o.maxit)) {
             TRY(read_scalars(ctx));
             const double *h = ctx.op->pinned;
@@ -102,8 +132,9 @@ int cg64(Ctx &ctx, const double *b, double *x, const mfhex_cg_opts &o, bool x0_z
             if (std::sqrt(h[kScRRNew]) <= o.rtol * bnorm) {
                 // the recursive residual claims convergence: accept only on the true residual,
                 // otherwise continue from the true residual (beta from it, direction kept)
-                const double rr_old = h[kScRRPrev];
+                const double rr_old = h[kScRRPrev], rz_old = h[kScRZPrev];
                 TRY(true_residual(ctx, b, x, ctx.r64, nullptr));
+                if (ctx.pre) TRY(precond_store(ctx, MFHEX_F64, ctx.r64, ctx.z64, kScRZTmp));
                 TRY(read_scalars(ctx));
                 double *hp = ctx.op->pinned;
                 if (std::sqrt(hp[kScRRTrue]) <= o.rtol * bnorm) {
@@ -111,15 +142,22 @@ int cg64(Ctx &ctx, const double *b, double *x, const mfhex_cg_opts &o, bool x0_z
                     break;
                 }
                 hp[kScRR] = hp[kScRRTrue];
-                hp[kScBeta] = hp[kScRRTrue] / rr_old;
+                if (ctx.pre) {
+                    hp[kScRZ] = hp[kScRZTmp];
+                    hp[kScBeta] = hp[kScRZTmp] / rz_old;
+                } else {
+                    hp[kScBeta] = hp[kScRRTrue] / rr_old;
+                }
                 HIP(hipMemcpyAsync(ctx.sc + kScRR, hp + kScRR, sizeof(double), hipMemcpyHostToDevice, ctx.s),
                     "write scalar");
                 HIP(hipMemcpyAsync(ctx.sc + kScBeta, hp + kScBeta, sizeof(double), hipMemcpyHostToDevice, ctx.s),
                     "write scalar");
+                HIP(hipMemcpyAsync(ctx.sc + kScRZ, hp + kScRZ, sizeof(double), hipMemcpyHostToDevice, ctx.s),
+                    "write scalar");
                 HIP(hipStreamSynchronize(ctx.s), "hipStreamSynchronize");
             }
         }
-        HIP(launch_update_p(ctx.r64, ctx.p64, MFHEX_F64, ctx.sc, n, ctx.s), "update kernel");
+        HIP(launch_update_p(zr, ctx.p64, MFHEX_F64, ctx.sc, n, ctx.s), "update kernel");
     }
     if (exact) {
         TRY(read_scalars(ctx));
@@ -139,6 +177,8 @@ int cg_solve(mfhex_op op, const double *b, double *x, void *work, const mfhex_cg
     if (op->d.ncomp != 1) return set_error(op, MFHEX_ERR_UNSUPPORTED, "CG solves one component (ncomp = 1)");
     if (o->maxit < 0 || !(o->rtol >= 0.0)) return set_error(op, MFHEX_ERR_ARG, "bad maxit or rtol");
     if (o->mode != MFHEX_CG_F64 && o->mode != MFHEX_CG_MIXED) return set_error(op, MFHEX_ERR_ARG, "bad CG mode");
+    if (o->precond != MFHEX_PRECOND_NONE && o->precond != MFHEX_PRECOND_JACOBI)
+        return set_error(op, MFHEX_ERR_ARG, "bad preconditioner");
     if (o->mode == MFHEX_CG_MIXED && !op->q32)
         return set_error(op, MFHEX_ERR_STATE, "mixed CG needs an operator created with MFHEX_FLAG_F32");
     if (o->mode == MFHEX_CG_MIXED && op->d.variable_kappa)
@@ -152,8 +192,15 @@ int cg_solve(mfhex_op op, const double *b, double *x, void *work, const mfhex_cg
             reinterpret_cast<double *>(w + L.ap64), reinterpret_cast<double *>(w + L.partial),
             reinterpret_cast<double *>(w + L.sc), reinterpret_cast<double *>(w + L.hist),
             reinterpret_cast<float *>(w + L.r32), reinterpret_cast<float *>(w + L.p32),
-            reinterpret_cast<float *>(w + L.ap32)};
+            reinterpret_cast<float *>(w + L.ap32), o->precond == MFHEX_PRECOND_JACOBI,
+            reinterpret_cast<double *>(w + L.z64), reinterpret_cast<double *>(w + L.dinv64),
+            reinterpret_cast<float *>(w + L.z32), reinterpret_cast<float *>(w + L.dinv32)};
     HIP(hipMemsetAsync(ctx.sc, 0, kNumSc * sizeof(double), s), "hipMemsetAsync");
+    if (ctx.pre) {
+        // operator diagonal into dinv64, inverted in place (FP32 copy for mixed mode)
+        TRY(diagonal_impl(op, ctx.dinv64, s));
+        HIP(launch_jacobi_inverse(ctx.dinv64, ctx.dinv64, ctx.dinv32, op->N, s), "inverse kernel");
+    }
     TRY(dot_store(ctx, b, MFHEX_F64, b, MFHEX_F64, kScBB));
     TRY(read_scalars(ctx));
     const double bnorm = std::sqrt(op->pinned[kScBB]);
@@ -181,7 +228,9 @@ int cg_solve(mfhex_op op, const double *b, double *x, void *work, const mfhex_cg
             TRY(true_residual(ctx, b, x, nullptr, ctx.r32));
         }
         TRY(dot_store(ctx, ctx.r32, MFHEX_F32, ctx.r32, MFHEX_F32, kScRR));
-        HIP(launch_copy(ctx.r32, MFHEX_F32, ctx.p32, MFHEX_F32, n, s), "copy kernel");
+        if (ctx.pre) TRY(precond_store(ctx, MFHEX_F32, ctx.r32, ctx.z32, kScRZ));
+        float *const zr = ctx.pre ? ctx.z32 : ctx.r32;
+        HIP(launch_copy(zr, MFHEX_F32, ctx.p32, MFHEX_F32, n, s), "copy kernel");
         TRY(read_scalars(ctx));
         double last_true = std::sqrt(op->pinned[kScRRTrue]);
         r0 = last_true;
@@ -195,11 +244,19 @@ int cg_solve(mfhex_op op, const double *b, double *x, void *work, const mfhex_cg
         while (iters < o->maxit) {
             TRY(apply_impl(op, MFHEX_F32, 1, ctx.p32, ctx.ap32, s, true, -1));
             HIP(launch_dot(ctx.p32, MFHEX_F32, ctx.ap32, MFHEX_F32, n, ctx.partial, s), "dot kernel");
-            HIP(launch_finalize(ctx.partial, ctx.sc, kFinAlpha, 0, nullptr, 0, s), "finalize kernel");
-            HIP(launch_update_xr(x, ctx.r32, ctx.p32, ctx.ap32, MFHEX_F32, ctx.sc, n, ctx.partial, s), "update kernel");
+            HIP(launch_finalize(ctx.partial, ctx.sc, ctx.pre ? kFinAlphaPre : kFinAlpha, 0, nullptr, 0, s),
+                "finalize kernel");
+            if (ctx.pre)
+                HIP(launch_update_xrz(x, ctx.r32, ctx.p32, ctx.ap32, ctx.dinv32, ctx.z32, MFHEX_F32, ctx.sc, n,
+                                      ctx.partial, s),
+                    "update kernel");
+            else
+                HIP(launch_update_xr(x, ctx.r32, ctx.p32, ctx.ap32, MFHEX_F32, ctx.sc, n, ctx.partial, s),
+                    "update kernel");
             ++iters;
             ++since;
-            HIP(launch_finalize(ctx.partial, ctx.sc, kFinBeta, iters, ctx.hist, kHist, s), "finalize kernel");
+            HIP(launch_finalize(ctx.partial, ctx.sc, ctx.pre ? kFinBetaPre : kFinBeta, iters, ctx.hist, kHist, s),
+                "finalize kernel");
             if (iters % every == 0 || iters == o->maxit) {
                 TRY(read_scalars(ctx));
                 const double *h = op->pinned;
@@ -210,9 +267,10 @@ int cg_solve(mfhex_op op, const double *b, double *x, void *work, const mfhex_cg
                 const double rec = std::sqrt(h[kScRRNew]);
                 if (rec <= delta * last_true || since >= repl_every || rec <= o->rtol * bnorm) {
                     // residual replacement with the FP64 true residual; beta from the new r
-                    const double rr_old = h[kScRRPrev];
+                    const double rr_old = h[kScRRPrev], rz_old = h[kScRZPrev];
                     TRY(true_residual(ctx, b, x, nullptr, ctx.r32));
                     TRY(dot_store(ctx, ctx.r32, MFHEX_F32, ctx.r32, MFHEX_F32, kScTmp));
+                    if (ctx.pre) TRY(precond_store(ctx, MFHEX_F32, ctx.r32, ctx.z32, kScRZTmp));
                     TRY(read_scalars(ctx));
                     ++out.replacements;
                     since = 0;
@@ -232,16 +290,24 @@ int cg_solve(mfhex_op op, const double *b, double *x, void *work, const mfhex_cg
                     }
                     last_true = tr;
                     // beta = (r_new . r_new) / (r_prev . r_prev), rr = r_new . r_new
+                    // (preconditioned: beta from r.z, rz = r_new . z_new)
                     op->pinned[kScRR] = op->pinned[kScTmp];
-                    op->pinned[kScBeta] = op->pinned[kScTmp] / rr_old;
+                    if (ctx.pre) {
+                        op->pinned[kScRZ] = op->pinned[kScRZTmp];
+                        op->pinned[kScBeta] = op->pinned[kScRZTmp] / rz_old;
+                    } else {
+                        op->pinned[kScBeta] = op->pinned[kScTmp] / rr_old;
+                    }
                     HIP(hipMemcpyAsync(ctx.sc + kScRR, op->pinned + kScRR, sizeof(double), hipMemcpyHostToDevice, s),
                         "write scalar");
                     HIP(hipMemcpyAsync(ctx.sc + kScBeta, op->pinned + kScBeta, sizeof(double), hipMemcpyHostToDevice, s),
                         "write scalar");
+                    HIP(hipMemcpyAsync(ctx.sc + kScRZ, op->pinned + kScRZ, sizeof(double), hipMemcpyHostToDevice, s),
+                        "write scalar");
                     HIP(hipStreamSynchronize(s), "hipStreamSynchronize");
                 }
             }
-            HIP(launch_update_p(ctx.r32, ctx.p32, MFHEX_F32, ctx.sc, n, s), "update kernel");
+            HIP(launch_update_p(zr, ctx.p32, MFHEX_F32, ctx.sc, n, s), "update kernel");
         }
         if (fallback && iters < o->maxit) {
             out.fell_back_to_f64 = 1;

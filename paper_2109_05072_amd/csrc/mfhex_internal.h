@@ -70,6 +70,15 @@ struct ApplyLaunch {
     hipStream_t stream;
 };
 
+// Diagonal of the assembled operator (FP64), accumulated into d.
+struct DiagLaunch {
+    OpView v;  // FP64 factors
+    int P, colloc, mode, vark;
+    const double *basis_dev;
+    double *d;
+    hipStream_t stream;
+};
+
 struct KgradLaunch {
     OpView v;
     int P, colloc;
@@ -145,10 +154,12 @@ constexpr int basis_len(int P, int Q) { return basis_dtf(P, Q) + half_up(Q) * Q;
 // Per-order dispatch (one translation unit per order, apply_p<N>.hip).
 hipError_t launch_apply(const ApplyLaunch &a);
 hipError_t launch_kgrad(const KgradLaunch &a);
+hipError_t launch_diag(const DiagLaunch &a);
 
 #define MFHEX_DECLARE_ORDER(N)                                  \
     hipError_t launch_apply_p##N(const ApplyLaunch &a);         \
-    hipError_t launch_kgrad_p##N(const KgradLaunch &a);
+    hipError_t launch_kgrad_p##N(const KgradLaunch &a);         \
+    hipError_t launch_diag_p##N(const DiagLaunch &a);
 MFHEX_DECLARE_ORDER(1)
 MFHEX_DECLARE_ORDER(2)
 MFHEX_DECLARE_ORDER(3)

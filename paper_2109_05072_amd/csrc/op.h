@@ -39,7 +39,7 @@ Layout workspace_layout(const mfhex_desc &d, int64_t E, int P, int Q);
 
 // Solver work layout for n nodes.
 struct CgLayout {
-    size_t r64, p64, ap64, r32, p32, ap32, partial, sc, hist, total;
+    size_t r64, p64, ap64, r32, p32, ap32, partial, sc, hist, z64, dinv64, z32, dinv32, total;
 };
 constexpr int kHist = 8192;
 CgLayout cg_layout(int64_t n);
@@ -54,6 +54,8 @@ int apply_impl(mfhex_op op, int prec, int nrhs, const void *x, void *y, hipStrea
 int default_variant(const mfhex_op_s &op, int prec, int nvec);
 bool valid_variant(const mfhex_op_s &op, int prec, int variant);
 LaunchCfg config_for(const mfhex_op_s &op, int prec, int nvec);
+// diag(M A M) (FP64, masked nodes 0) into d [N].
+int diagonal_impl(mfhex_op op, double *d, hipStream_t s);
 int default_chain(const mfhex_op_s &op);
 int mode_of(const mfhex_op_s &op);
 

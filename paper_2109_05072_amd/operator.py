@@ -140,6 +140,12 @@ class Operator:
         L.mfhex_kappa_grad(self.handle, u.data_ptr(), r.data_ptr(), g.data_ptr(), _stream())
         return g
 
+    def diagonal(self) -> torch.Tensor:
+        """Diagonal of the assembled operator (FP64, [n_nodes], 0 at masked nodes)."""
+        d = torch.empty(self.n_nodes, dtype=torch.float64, device=self.device)
+        L.mfhex_diagonal(self.handle, d.data_ptr(), _stream())
+        return d
+
     def qpoint_coords(self) -> torch.Tensor:
         xyz = torch.empty(self.n_elem, self.q ** 3, 3, dtype=torch.float64, device=self.device)
         L.mfhex_qpoint_coords(self.handle, xyz.data_ptr(), _stream())
@@ -160,15 +166,21 @@ class Operator:
     # -- solver ------------------------------------------------------------------------------
     def cg(self, b: torch.Tensor, x: Optional[torch.Tensor] = None, maxit: int = 1000, rtol: float = 1e-10,
            mode: str = "f64", check_every: int = 1, replace_every: int = 100, replace_delta: float = 0.1,
-           exact_iters: bool = False) -> CGResult:
+           exact_iters: bool = False, precond: str = "none") -> CGResult:
+        """Solve A x = b by CG: mode "f64" or "mixed" (reliable updates), precond "none" or "jacobi"."""
         self._check_vec(b, 1)
         if self._cg_work is None:
             self._cg_work = torch.empty(int(self.sizes.cg_work_bytes) + 256, dtype=torch.uint8, device=self.device)
         work = (self._cg_work.data_ptr() + 255) & ~255
         x0_zero = x is None
         x = torch.zeros_like(b) if x is None else x
-        opts = L.mfhex_cg_opts(maxit, check_every, L.MFHEX_CG_MIXED if mode == "mixed" else L.MFHEX_CG_F64,
-                               replace_every, int(x0_zero), int(exact_iters), rtol, replace_delta)
+        if precond not in ("none", "jacobi"):
+            raise ValueError(f"unknown preconditioner {precond!r}")
+        opts = L.mfhex_cg_opts(maxit=maxit, check_every=check_every,
+                               mode=L.MFHEX_CG_MIXED if mode == "mixed" else L.MFHEX_CG_F64,
+                               replace_every=replace_every, x0_is_zero=int(x0_zero), max_iters_exact=int(exact_iters),
+                               precond=L.MFHEX_PRECOND_JACOBI if precond == "jacobi" else L.MFHEX_PRECOND_NONE,
+                               rtol=rtol, replace_delta=replace_delta)
         hist = np.zeros(min(maxit, 8191) + 1)
         code, st = L.mfhex_cg(self.handle, b.data_ptr(), x.data_ptr(), work, opts,
                               hist.ctypes.data_as(C.POINTER(C.c_double)), _stream())

@@ -115,3 +115,12 @@ def test_library_bases_match_the_mathematics(p, quad):
     for k in range(q):
         dk = k * xq ** (k - 1) if k else np.zeros(q)
         np.testing.assert_allclose(D @ xq ** k, dk, atol=5e-12 * max(1, k))
+
+
+def test_cg_option_struct_layout():
+    # int32 maxit, check_every, mode, replace_every, x0_is_zero, max_iters_exact, precond, pad_;
+    # double rtol, replace_delta -- the binding must agree with the header byte for byte
+    assert C.sizeof(L.mfhex_cg_opts) == 48
+    assert L.mfhex_cg_opts.rtol.offset == 32 and L.mfhex_cg_opts.precond.offset == 24
+    src = open(os.path.join(ROOT, "include", "mfhex.h")).read()
+    assert "max_iters_exact, precond, pad_;" in src

@@ -369,6 +369,97 @@ def test_cg_solution_and_mixed_precision(gpu_lib, p):
     assert np.abs(x64 - ue).max() < 1e-2
 
 
+# --- operator diagonal and Jacobi-preconditioned CG -----------------------------------------
+
+@pytest.mark.parametrize("p", range(1, 9))
+@pytest.mark.parametrize("kind,quad", [("diffusion", "gauss"), ("diffusion", "gll"), ("mass", "gauss")])
+@pytest.mark.parametrize("dirichlet", [True, False])
+def test_diagonal_matches_oracle(gpu_lib, p, kind, quad, dirichlet):
+    _say("diagonal", p, kind, quad, dirichlet)
+    op, pr = build(gpu_lib, 3, 2, 2, p, kind, quad, dirichlet)
+    d = host(op.diagonal())
+    assert relerr(d, oracle.diagonal(pr)) <= TOL64
+    if dirichlet:
+        inner = interior_mask(pr) > 0
+        assert np.all(d[~inner] == 0.0) and np.all(d[inner] > 0.0)
+
+
+@pytest.mark.parametrize("p,quad", [(2, "gauss"), (5, "gauss"), (3, "gll")])
+def test_diagonal_variable_kappa_matches_oracle(gpu_lib, p, quad):
+    op, pr = build(gpu_lib, 3, 2, 2, p, "diffusion", quad, True, vark=True)
+    kap = synth.kappa_field(host(op.qpoint_coords()))
+    pr = pr.with_(kappa=synth.kappa_field(oracle.qpoint_geometry(pr)[0]))
+    op.set_kappa(dev(kap))
+    assert relerr(host(op.diagonal()), oracle.diagonal(pr)) <= TOL64
+
+
+def test_config0_fifty_pcg_iterations_match_oracle(gpu_lib):
+    # config-0 mesh (4x4x4, p = 2, Gauss q = 4, Dirichlet), 50 Jacobi-preconditioned iterations
+    op, pr = build(gpu_lib, 4, 4, 4, 2)
+    b = synth.uniform_vector(pr.n_nodes, seed=3) * interior_mask(pr)
+    dinv = oracle.jacobi_inverse(oracle.diagonal(pr))
+    xo, ho, it, _ = oracle.pcg(pr, b, dinv, maxit=50, rtol=0.0)
+    assert it == 50
+    res = op.cg(dev(b), maxit=50, rtol=0.0, exact_iters=True, precond="jacobi")
+    xg = host(res.x)
+    print("config0 pcg x50 rel diff", relerr(xg, xo), "history max rel diff", relerr(res.history, ho))
+    assert res.iters == 50
+    assert relerr(xg, xo) <= 1e-10
+    assert np.all(np.abs(res.history - ho) <= 1e-10 * ho + 1e-14 * ho[0])
+
+
+@pytest.mark.parametrize("p", [2, 3])
+def test_pcg_solution_and_mixed_precision(gpu_lib, p):
+    ne = 12 if p == 2 else 8
+    op, pr = build(gpu_lib, ne, ne, ne, p, "diffusion", "gauss", True, f32=True, rhs=True)
+    b = _masked_rhs(op, pr)
+    r0 = op.cg(b, maxit=5000, rtol=1e-10, mode="f64")
+    r64 = op.cg(b, maxit=5000, rtol=1e-10, mode="f64", precond="jacobi")
+    rmx = op.cg(b, maxit=5000, rtol=1e-10, mode="mixed", precond="jacobi")
+    print("cg", r0.iters, "pcg f64", r64.iters, r64.rel_resid_true, "pcg mixed", rmx.iters, rmx.replacements,
+          rmx.rel_resid_true, rmx.fell_back_to_f64)
+    assert r64.status == 0 and r64.rel_resid_true <= 1e-10
+    assert rmx.status == 0 and rmx.rel_resid_true <= 1e-10
+    assert r64.iters <= r0.iters
+    bo = oracle.rhs(pr, synth.sin_forcing(oracle.qpoint_geometry(pr)[0]))
+    xo, _, _, code = oracle.pcg(pr, bo, oracle.jacobi_inverse(oracle.diagonal(pr)), maxit=5000, rtol=1e-12)
+    assert code == oracle.OK
+    assert relerr(host(r64.x), xo) <= 1e-7
+    assert relerr(host(rmx.x), xo) <= 1e-7
+
+
+def test_pcg_high_contrast_coefficient(gpu_lib):
+    # kappa = 10^(4x): Jacobi removes the coefficient scale, far fewer iterations than plain CG
+    op, pr = build(gpu_lib, 6, 6, 6, 2, "diffusion", "gauss", True, vark=True)
+    xq = host(op.qpoint_coords())
+    kap = 10.0 ** (4.0 * xq[:, :, 0])
+    op.set_kappa(dev(kap))
+    pr = pr.with_(kappa=10.0 ** (4.0 * oracle.qpoint_geometry(pr)[0].reshape(pr.n_elem, -1, 3)[:, :, 0]))
+    b = synth.uniform_vector(pr.n_nodes, seed=4) * interior_mask(pr)
+    rc = op.cg(dev(b), maxit=20000, rtol=1e-10)
+    rp = op.cg(dev(b), maxit=20000, rtol=1e-10, precond="jacobi")
+    print("high contrast: cg", rc.iters, "pcg", rp.iters)
+    assert rc.status == 0 and rp.status == 0
+    assert rp.iters < 0.5 * rc.iters
+    xo, _, _, _ = oracle.pcg(pr, b, oracle.jacobi_inverse(oracle.diagonal(pr)), maxit=20000, rtol=1e-12)
+    assert relerr(host(rp.x), xo) <= 1e-7
+
+
+def test_pcg_rejects_unknown_preconditioner(gpu_lib):
+    import ctypes as C
+    from paper_2109_05072_amd import _lib as L
+    op, pr = build(gpu_lib, 2, 2, 2, 2)
+    b = dev(synth.uniform_vector(pr.n_nodes) * interior_mask(pr))
+    x = torch.zeros_like(b)
+    work = torch.empty(int(op.sizes.cg_work_bytes) + 256, dtype=torch.uint8, device="cuda")
+    wp = (work.data_ptr() + 255) & ~255
+    opts = L.mfhex_cg_opts(maxit=10, check_every=1, mode=L.MFHEX_CG_F64, replace_every=100, x0_is_zero=1,
+                           max_iters_exact=0, precond=7, rtol=1e-10, replace_delta=0.1)
+    with pytest.raises(L.MFHexError) as ei:
+        L.mfhex_cg(op.handle, b.data_ptr(), x.data_ptr(), wp, opts, None, torch.cuda.current_stream().cuda_stream)
+    assert ei.value.code == L.MFHEX_ERR_ARG
+
+
 # --- error paths -----------------------------------------------------------------------------
 
 def test_error_paths(gpu_lib):
