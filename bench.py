@@ -358,6 +358,8 @@ def cg_compare(orders=(3, 5, 7), dofs=3e7):
         b = op.rhs(torch.from_numpy(f).cuda())
         r64 = op.cg(b, maxit=20000, rtol=1e-10, mode="f64")
         rmx = op.cg(b, maxit=20000, rtol=1e-10, mode="mixed")
+        j64 = op.cg(b, maxit=20000, rtol=1e-10, mode="f64", precond="jacobi")
+        jmx = op.cg(b, maxit=20000, rtol=1e-10, mode="mixed", precond="jacobi")
         d = float((rmx.x - r64.x).norm() / r64.x.norm())
         ue = torch.from_numpy(synth.sin_solution(op.node_coords().cpu().numpy())).cuda()
         res.append({"p": p, "dofs": op.n_nodes, "f64_s": round(r64.seconds, 4), "f64_iters": r64.iters,
@@ -366,7 +368,13 @@ def cg_compare(orders=(3, 5, 7), dofs=3e7):
                     "rel_diff_x_mixed_vs_f64": d, "f64_rel_resid": r64.rel_resid_true,
                     "mixed_rel_resid": rmx.rel_resid_true,
                     "max_err_vs_exact_f64": float((r64.x - ue).abs().max()),
-                    "max_err_vs_exact_mixed": float((rmx.x - ue).abs().max())})
+                    "max_err_vs_exact_mixed": float((rmx.x - ue).abs().max()),
+                    "jacobi_f64_s": round(j64.seconds, 4), "jacobi_f64_iters": j64.iters,
+                    "jacobi_mixed_s": round(jmx.seconds, 4), "jacobi_mixed_iters": jmx.iters,
+                    "jacobi_mixed_replacements": jmx.replacements, "jacobi_f64_rel_resid": j64.rel_resid_true,
+                    "jacobi_mixed_rel_resid": jmx.rel_resid_true,
+                    "jacobi_rel_diff_x_vs_f64": float((j64.x - r64.x).norm() / r64.x.norm()),
+                    "speedup_jacobi_mixed_vs_f64": round(r64.seconds / jmx.seconds, 3)})
         print(f"# cg {res[-1]}", file=sys.stderr, flush=True)
         op.close()
         del op
