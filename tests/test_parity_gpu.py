@@ -518,23 +518,33 @@ def _window_value(vert_full, nex, ney, nez, p, quad, kind, dirichlet, x_full, no
     return yw[li]
 
 
-@pytest.mark.parametrize("p", [3, 8])
-def test_full_size_sampled_against_oracle(gpu_lib, p):
+@pytest.mark.parametrize("p", [3, 4, 5, 6, 7, 8])
+@pytest.mark.parametrize("kind", ["diffusion", "mass"])
+def test_full_size_sampled_against_oracle(gpu_lib, p, kind):
+    """The benchmark's operators (about 1e7 nodes, default launch configuration) sampled node by
+    node: random nodes, nodes near corners, and nodes on the x-faces inside and between element
+    groups (summed on chip before one atomic)."""
     ne = synth.elems_for_dofs(1e7, p)
-    _say("full size", p, ne)
-    op, _ = build(gpu_lib, ne, ne, ne, p, "diffusion", "gauss", True)
+    dirichlet = kind == "diffusion"
+    _say("full size", p, kind, ne)
+    op, _ = build(gpu_lib, ne, ne, ne, p, kind, "gauss", dirichlet)
+    _say("launch", op.get_config())
     vert = synth.mesh_vertices(ne, ne, ne)
     x = synth.uniform_vector(op.n_nodes)
     y = host(op.apply(dev(x)))
     rng = np.random.default_rng(17)
     n = p * ne + 1
-    nodes = list(rng.integers(0, op.n_nodes, size=24))
+    nodes = list(rng.integers(0, op.n_nodes, size=20))
     nodes += [1 + n + n * n, (n - 2) + n * (n - 2) + n * n * (n - 2), p + n * p + n * n * p]  # near corners, vertex
+    J = K = 2 * p + 1
+    nodes += [m * p + n * (J + n * K) for m in range(1, 10)]  # x-faces of the first element groups of a row
+    nodes += [m * p + n * (p * 3 + n * p * 5) for m in range(1, 10)]  # ... on element edges in y and z too
     scale = np.abs(y).max()
+    kd = oracle.DIFFUSION if kind == "diffusion" else oracle.MASS
     for node in nodes:
-        I, J, K = node % n, (node // n) % n, node // (n * n)
-        if min(I, J, K) == 0 or max(I, J, K) == n - 1:
+        I, J_, K_ = node % n, (node // n) % n, node // (n * n)
+        if dirichlet and (min(I, J_, K_) == 0 or max(I, J_, K_) == n - 1):
             assert y[node] == 0.0
             continue
-        yo = _window_value(vert, ne, ne, ne, p, oracle.GAUSS, oracle.DIFFUSION, True, x, node)
+        yo = _window_value(vert, ne, ne, ne, p, oracle.GAUSS, kd, dirichlet, x, node)
         assert abs(y[node] - yo) <= TOL64 * scale, (node, y[node], yo)
