@@ -34,6 +34,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "GDOF/s of BP3 apply per order p; mixed-vs-FP64 CG time to 1e-10 resid"
 HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6  # MI355X dense FP64 (vector and matrix)
 PAPER_V100_CUDA_GEN = {1: 0.510, 2: 1.420, 3: 1.872, 4: 2.300, 5: 2.344, 6: 2.683, 7: 2.639, 8: 2.609}
 
 
@@ -41,12 +42,20 @@ def alg_bytes(N: int, E: int, p: int, q: int, g: int = 6, s: int = 8, nvec: int 
     return s * N * nvec * 2 + 4 * E * (p + 1) ** 3 + s * g * E * q ** 3
 
 
-def alg_flops(E: int, p: int, q: int, kind: str = "diffusion", colloc: bool = False) -> int:
+def alg_flops(E: int, p: int, q: int, kind: str = "diffusion", colloc: bool = False, otf: bool = False) -> int:
     P, Q = p + 1, q
     interp = 0 if colloc else 4 * (Q * P ** 3 + Q * Q * P * P + Q ** 3 * P)
     if kind == "mass":
         return E * (interp + Q ** 3)
-    return E * (interp + 12 * Q ** 4 + 15 * Q ** 3)
+    # in-kernel factors: 3 adjugate rows (27), detJ (5), 6 products (30), scaling (8) per point,
+    # and 3 Q^2 Jacobian columns (36 each) per element
+    geo = (70 * Q ** 3 + 108 * Q ** 2) if otf else 0
+    return E * (interp + 12 * Q ** 4 + 15 * Q ** 3 + geo)
+
+
+def alg_bytes_otf(N: int, E: int, ne: int, p: int) -> int:
+    """In-kernel factors: x, y, offsets and the vertex coordinates (each vertex read once)."""
+    return 8 * N * 2 + 4 * E * (p + 1) ** 3 + 24 * (ne + 1) ** 3
 
 
 def cpu_baseline(p: int, budget_s: float = 12.0) -> dict:
@@ -92,6 +101,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cg", action="store_true", help="also time FP64 vs mixed CG to 1e-10")
     ap.add_argument("--tune", action="store_true", help="autotune the launch variant before timing")
+    ap.add_argument("--otf", action="store_true",
+                    help="diffusion with the geometric factors evaluated in the kernel (no stored factors)")
     ap.add_argument("--sweep", action="store_true", help="report the time of every launch variant (stderr)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="after timing, copy 1 GiB device-to-device twice (a kernel of known traffic, "
@@ -113,7 +124,8 @@ def main():
     for p in orders:
         ne = synth.elems_for_dofs(args.dofs, p)
         vert = synth.mesh_vertices(ne, ne, ne)
-        op = mf.Operator(ne, ne, ne, p, vert, kind=args.kind, quad="gauss", dirichlet=(args.kind == "diffusion"))
+        op = mf.Operator(ne, ne, ne, p, vert, kind=args.kind, quad="gauss", dirichlet=(args.kind == "diffusion"),
+                         otf=args.otf)
         x = torch.from_numpy(synth.uniform_vector(op.n_nodes)).cuda()
         ops[p], xs[p], ys[p] = op, x, torch.empty_like(x)
         if args.sweep:
@@ -150,12 +162,15 @@ def main():
     for p in orders:
         t_ms = float(np.mean([a.elapsed_time(b) for a, b in evs[p]]))
         m = meta[p]
-        byts = alg_bytes(m["N"], m["E"], p, m["q"], g=6 if args.kind == "diffusion" else 1)
+        byts = (alg_bytes_otf(m["N"], m["E"], m["ne"], p) if args.otf else
+                alg_bytes(m["N"], m["E"], p, m["q"], g=6 if args.kind == "diffusion" else 1))
+        fl = alg_flops(m["E"], p, m["q"], args.kind, otf=args.otf)
         gbs = byts / (t_ms / 1e3) / 1e9
         per_p.append({"p": p, "elements_per_dim": m["ne"], "dofs": m["N"], "ms": round(t_ms, 4),
                       "gdofs": round(m["N"] / (t_ms / 1e3) / 1e9, 3), "alg_bytes": byts,
                       "alg_gbs": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
-                      "alg_tflops": round(alg_flops(m["E"], p, m["q"], args.kind) / (t_ms / 1e3) / 1e12, 2),
+                      "alg_tflops": round(fl / (t_ms / 1e3) / 1e12, 2),
+                      "fp64_alu_frac": round(fl / (t_ms / 1e3) / 1e12 / FP64_PEAK_TFLOPS, 4),
                       "launch": {"variant": m["epb"][0], "elements_per_group": m["epb"][1],
                                  "threads_per_group": m["epb"][2], "groups_per_block": m["epb"][3]},
                       "paper_v100_cuda_gen_gdofs": PAPER_V100_CUDA_GEN.get(p)})
@@ -163,8 +178,9 @@ def main():
     from paper_2109_05072_amd.prof_summary import read_traffic
     lg = dom["launch"]
     if args.kind == "diffusion":
-        traffic = read_traffic(os.path.join(ROOT, "profiles", "bp3_apply_traffic.txt"))
-        dom_name = (f"k_apply p={dom['p']} q={dom['p'] + 2} diffusion double G={lg['elements_per_group']} "
+        tag = "otf " if args.otf else ""
+        traffic = read_traffic(os.path.join(ROOT, "profiles", f"bp3{'_otf' if args.otf else ''}_apply_traffic.txt"))
+        dom_name = (f"k_apply p={dom['p']} q={dom['p'] + 2} diffusion {tag}double G={lg['elements_per_group']} "
                     f"NT={lg['threads_per_group']}")
     else:
         traffic = read_traffic(os.path.join(ROOT, "profiles", "bp1_apply_traffic.txt"))
@@ -175,16 +191,22 @@ def main():
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
         "data": "synthetic (seeded perturbed unit-cube hex meshes, U[-1,1] inputs)",
-        "config": {"workload": (f"BP3 diffusion apply FP64, Gauss q=p+2, p={','.join(map(str, orders))}, "
+        "config": {"workload": (f"BP3 diffusion apply FP64{' (geometric factors in-kernel)' if args.otf else ''}, "
+                                f"Gauss q=p+2, p={','.join(map(str, orders))}, "
                                 f"~{args.dofs:.0e} DOFs per order, perturbed hex mesh, Dirichlet")
                    if args.kind == "diffusion" else
                                (f"BP1 mass apply FP64, Gauss q=p+2, p={','.join(map(str, orders))}, "
                                 f"~{args.dofs:.0e} DOFs per order, perturbed hex mesh"),
                    "orders": orders, "dofs_per_step": dofs_per_step},
-        "roofline": {"bound": "hbm", "kernel": dom_name,
-                     "achieved": dom["alg_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": dom["hbm_frac"], "traffic": traffic.get(dom_name),
-                     "alg_bytes_per_launch": dom["alg_bytes"]},
+        "roofline": ({"bound": "hbm", "kernel": dom_name,
+                      "achieved": dom["alg_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                      "frac": dom["hbm_frac"], "traffic": traffic.get(dom_name),
+                      "alg_bytes_per_launch": dom["alg_bytes"]}
+                     if not args.otf or dom["hbm_frac"] >= dom["fp64_alu_frac"] else
+                     {"bound": "alu", "kernel": dom_name, "achieved": dom["alg_tflops"],
+                      "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": dom["fp64_alu_frac"],
+                      "traffic": traffic.get(dom_name), "alg_bytes_per_launch": dom["alg_bytes"],
+                      "hbm_frac": dom["hbm_frac"]}),
         "per_order": per_p,
     }
     if args.calib_copy:

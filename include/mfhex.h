@@ -64,6 +64,11 @@ enum { MFHEX_PRECOND_NONE = 0, MFHEX_PRECOND_JACOBI = 1 }; /* CG preconditioner 
 /* desc.flags bits */
 #define MFHEX_FLAG_F32 1u  /* also build FP32 quadrature data (for prec = MFHEX_F32) */
 #define MFHEX_FLAG_RHS 2u  /* keep w*detJ per point for mfhex_rhs on a diffusion op  */
+#define MFHEX_FLAG_OTF 4u  /* diffusion, FP64, constant kappa: no stored geometric factors; the apply
+                            * evaluates w adj(J) adj(J)^T / detJ at every point from the element's 8
+                            * vertices (the factors equal the stored ones up to rounding).  The
+                            * workspace then holds no factor array; mfhex_diagonal (and so the
+                            * Jacobi-preconditioned CG) is not available on such an operator. */
 
 /* Operator description.
  *   p in [1,8].  quad = MFHEX_GAUSS needs q = p+2 (mass and stiffness);

@@ -33,6 +33,7 @@
 #pragma once
 
 #include "diag_kernels.hpp"
+#include "geom.hpp"
 #include "mfhex_internal.h"
 
 namespace mfhex {
@@ -332,21 +333,34 @@ __device__ __forceinline__ void grad(T *s0, T *s1, T *s2, const T *__restrict__ 
 // y += A x  (diffusion), or y += B^T (w detJ f) for the load vector.
 // VC vectors of the multi-vector travel together (virtual elements g*VC + vc).
 // ---------------------------------------------------------------------------
-template <int P, int Q, bool COLLOC, int MODE, bool VARK, typename T, int G, int NT, int VC>
+//
+// OTF (diffusion, FP64, constant coefficient): no stored factors.  Along a
+// trilinear map dx/dr depends on (s, t) only, dx/ds on (r, t) and dx/dt on
+// (r, s), so each element's Jacobian is fully described by three tables of
+// Q^2 columns, built once per element group in LDS from its 8 vertices; each
+// point then reads its three columns and forms w adj(J) adj(J)^T / detJ in
+// registers (the same expressions as the set-up kernel), instead of reading
+// six factors per point from HBM.
+template <int P, int Q, bool COLLOC, int MODE, bool VARK, typename T, int G, int NT, int VC, bool OTF = false>
 __global__ void __launch_bounds__(NT)
-k_apply(const T *__restrict__ bas, const int nex, const int nvec, const int32_t *__restrict__ offsets,
+k_apply(const T *__restrict__ bas, const int nex, const int ney, const int nvec, const int32_t *__restrict__ offsets,
         const T *__restrict__ qdata, const double *__restrict__ kappa, const double *__restrict__ wdet,
-        const T *__restrict__ x, T *__restrict__ y)
+        const double *__restrict__ vert, const T *__restrict__ x, T *__restrict__ y)
 {
     constexpr int Q2 = Q * Q, Q3 = Q2 * Q;
     constexpr int NPT = G * Q3, RQ = (NPT + NT - 1) / NT;
     constexpr int GV = G * VC;
     static_assert(MODE != kMass, "the mass operator runs in k_mass");
+    static_assert(!OTF || (MODE == kDiff && !VARK && VC == 1 && sizeof(T) == 8), "in-kernel factors: FP64 diffusion");
     using L = Lds<Q>;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T *const s0 = reinterpret_cast<T *>(smem_raw);
     T *const s1 = s0 + GV * L::BUF;
     T *const s2 = s1 + GV * L::BUF;
+    // OTF: element vertices [G][8][3], 1D rule x [Q], w [Q] (one contiguous run), Jacobian columns [G][3][Q^2][3]
+    double *const sV = reinterpret_cast<double *>(s2 + GV * L::BUF);
+    double *const sR = sV + G * 24;
+    double *const sJ = sR + 2 * Q;
     const int tid = threadIdx.x;
     const GroupPos gpos = group_pos<G>(xcd_block(blockIdx.x, gridDim.x), nex);
     const int64_t e0 = gpos.e0;
@@ -355,10 +369,27 @@ k_apply(const T *__restrict__ bas, const int nex, const int nvec, const int32_t 
     int32_t off[NodeIO<P, G, NT, VC>::NR];
     load_offsets<P, G, NT, VC>(off, offsets, e0, nvalid, tid);
 
+    // OTF: the group's vertex coordinates, issued now, stored to LDS after the gather is issued
+    constexpr int VR = OTF ? (24 * G + 2 * Q + NT - 1) / NT : 1;
+    double vtx[VR];
+    if constexpr (OTF) {
+#pragma unroll
+        for (int r = 0; r < VR; ++r) {
+            const int t = tid + r * NT;
+            if (t < 24 * G) {
+                const int g = t / 24, v = (t % 24) / 3, d = t % 3;
+                const int64_t e = g < nvalid ? e0 + g : e0;
+                vtx[r] = vert[3 * elem_vertex(e, nex, ney, v) + d];
+            } else if (t < 24 * G + 2 * Q) {
+                vtx[r] = bas[basis_xq(P, Q) + (t - 24 * G)];  // x [Q] then w [Q], contiguous
+            }
+        }
+    }
+
     // This lane's geometric factors, loaded once per element group and issued
     // first, so their HBM latency overlaps the gather and the forward
     // contractions, and every chunk of vectors reuses them.
-    constexpr int NQD = MODE == kDiff ? kQdDiff : 0;
+    constexpr int NQD = MODE == kDiff && !OTF ? kQdDiff : 0;
     T qv[RQ][NQD > 0 ? NQD : 1];
     if constexpr (NQD > 0) {
 #pragma unroll
@@ -394,7 +425,32 @@ k_apply(const T *__restrict__ bas, const int nex, const int nvec, const int32_t 
             }
             group_sync<NT>();
         } else {
-            gather<P, Q, G, NT, VC, T>(s0, off, x, nvec, v0, nvalid, tid);
+            if constexpr (OTF) {
+                T xv[NodeIO<P, G, NT, VC>::NR];
+                gather_load<P, G, NT, VC>(xv, off, x, nvec, v0, tid);
+                if (v0 == 0) {
+                    // vertices and rule into LDS, then the Jacobian-column tables (the x loads stay in flight)
+#pragma unroll
+                    for (int r = 0; r < VR; ++r)
+                        if (tid + r * NT < 24 * G + 2 * Q) sV[tid + r * NT] = vtx[r];
+                    group_sync<NT>();
+                    for (int t = tid; t < G * 3 * Q2; t += NT) {
+                        const int g = t / (3 * Q2), dir = (t / Q2) % 3, uw = t % Q2;
+                        const double u = sR[uw % Q], w = sR[uw / Q];
+                        const double *Xg = sV + g * 24;
+                        auto X = [&](int v, int d) { return Xg[3 * v + d]; };
+                        double j[3];
+                        if (dir == 0) jacobian_col<0>(X, u, w, j);
+                        else if (dir == 1) jacobian_col<1>(X, u, w, j);
+                        else jacobian_col<2>(X, u, w, j);
+#pragma unroll
+                        for (int d = 0; d < 3; ++d) sJ[3 * t + d] = j[d];
+                    }
+                }
+                gather_store<P, Q, G, NT, VC>(s0, xv, off, nvec, v0, nvalid, tid);
+            } else {
+                gather<P, Q, G, NT, VC, T>(s0, off, x, nvec, v0, nvalid, tid);
+            }
             group_sync<NT>();
             interp<P, Q, COLLOC, GV, NT, T>(s0, bas, tid);
             {
@@ -407,6 +463,16 @@ k_apply(const T *__restrict__ bas, const int nex, const int nvec, const int32_t 
                         const int a = pt % Q, b = (pt / Q) % Q, c = pt / Q2;
                         const int loc = a + L::PITCH * b + L::PLANE * c;
                         const T *gm = qv[k];
+                        double gotf[kQdDiff];
+                        if constexpr (OTF) {
+                            // columns dx/dr at (b, c), dx/ds at (a, c), dx/dt at (a, b) of element g
+                            const double *Jg = sJ + g * 9 * Q2;
+                            const double *jr = Jg + 3 * (b + Q * c), *js = Jg + 3 * (Q2 + a + Q * c),
+                                         *jt = Jg + 3 * (2 * Q2 + a + Q * b);
+                            const double wq = sR[Q + a] * sR[Q + b] * sR[Q + c];
+                            diffusion_factors(jr, js, jt, wq, gotf);
+                            gm = gotf;
+                        }
 #pragma unroll
                         for (int vc = 0; vc < VC; ++vc) {
                             const int ls = (g * VC + vc) * L::BUF + loc;
@@ -608,13 +674,13 @@ static hipError_t prepare_lds(K kernel, size_t lds)
     return hipSuccess;
 }
 
-template <int P, int Q, bool COLLOC, int MODE, bool VARK, typename T, int V>
+template <int P, int Q, bool COLLOC, int MODE, bool VARK, typename T, int V, bool OTF = false>
 static hipError_t launch_apply_v(const ApplyLaunch &a)
 {
     constexpr int G = variant_g(Q, V, MODE), NT = variant_nt(Q, V), VC = variant_vc(V);
-    constexpr size_t lds = apply_lds(Q, MODE, sizeof(T), V);
+    constexpr size_t lds = apply_lds(Q, MODE, sizeof(T), V, OTF);
     // chunked multi-vector variants exist for the plain mass / diffusion operators only
-    if constexpr ((VC > 1 && (MODE == kRhs || VARK)) || lds > kMaxLds) {
+    if constexpr ((VC > 1 && (MODE == kRhs || VARK || OTF)) || lds > kMaxLds) {
         (void)a;
         return hipErrorInvalidValue;
     } else if constexpr (MODE == kMass) {
@@ -628,27 +694,27 @@ static hipError_t launch_apply_v(const ApplyLaunch &a)
         return hipGetLastError();
     } else {
         const int64_t nblk = (int64_t)a.v.ney * a.v.nez * ((a.v.nex + G - 1) / G);
-        auto kern = k_apply<P, Q, COLLOC, MODE, VARK, T, G, NT, VC>;
+        auto kern = k_apply<P, Q, COLLOC, MODE, VARK, T, G, NT, VC, OTF>;
         hipLaunchKernelGGL(kern, dim3((unsigned)nblk), dim3(NT), lds, a.stream, static_cast<const T *>(a.basis_dev),
-                           a.v.nex, a.nvec, a.v.offsets, static_cast<const T *>(a.v.qdata), a.v.kappa, a.wdet,
-                           static_cast<const T *>(a.x), static_cast<T *>(a.y));
+                           a.v.nex, a.v.ney, a.nvec, a.v.offsets, static_cast<const T *>(a.v.qdata), a.v.kappa,
+                           a.wdet, a.vert, static_cast<const T *>(a.x), static_cast<T *>(a.y));
         return hipGetLastError();
     }
 }
 
-template <int P, int Q, bool COLLOC, int MODE, bool VARK, typename T>
+template <int P, int Q, bool COLLOC, int MODE, bool VARK, typename T, bool OTF = false>
 static hipError_t launch_apply_t(const ApplyLaunch &a)
 {
     switch (a.variant) {
-    case 8: return launch_apply_v<P, Q, COLLOC, MODE, VARK, T, 8>(a);
-    case 0: return launch_apply_v<P, Q, COLLOC, MODE, VARK, T, 0>(a);
-    case 1: return launch_apply_v<P, Q, COLLOC, MODE, VARK, T, 1>(a);
-    case 2: return launch_apply_v<P, Q, COLLOC, MODE, VARK, T, 2>(a);
-    case 3: return launch_apply_v<P, Q, COLLOC, MODE, VARK, T, 3>(a);
-    case 4: return launch_apply_v<P, Q, COLLOC, MODE, VARK, T, 4>(a);
-    case 5: return launch_apply_v<P, Q, COLLOC, MODE, VARK, T, 5>(a);
-    case 6: return launch_apply_v<P, Q, COLLOC, MODE, VARK, T, 6>(a);
-    case 7: return launch_apply_v<P, Q, COLLOC, MODE, VARK, T, 7>(a);
+    case 8: return launch_apply_v<P, Q, COLLOC, MODE, VARK, T, 8, OTF>(a);
+    case 0: return launch_apply_v<P, Q, COLLOC, MODE, VARK, T, 0, OTF>(a);
+    case 1: return launch_apply_v<P, Q, COLLOC, MODE, VARK, T, 1, OTF>(a);
+    case 2: return launch_apply_v<P, Q, COLLOC, MODE, VARK, T, 2, OTF>(a);
+    case 3: return launch_apply_v<P, Q, COLLOC, MODE, VARK, T, 3, OTF>(a);
+    case 4: return launch_apply_v<P, Q, COLLOC, MODE, VARK, T, 4, OTF>(a);
+    case 5: return launch_apply_v<P, Q, COLLOC, MODE, VARK, T, 5, OTF>(a);
+    case 6: return launch_apply_v<P, Q, COLLOC, MODE, VARK, T, 6, OTF>(a);
+    case 7: return launch_apply_v<P, Q, COLLOC, MODE, VARK, T, 7, OTF>(a);
     default: return hipErrorInvalidValue;
     }
 }
@@ -663,6 +729,7 @@ static hipError_t launch_apply_pq(const ApplyLaunch &a)
     }
     if (a.mode == kMass) return launch_apply_t<P, Q, COLLOC, kMass, false, double>(a);
     if (a.vark) return launch_apply_t<P, Q, COLLOC, kDiff, true, double>(a);
+    if (a.otf) return launch_apply_t<P, Q, COLLOC, kDiff, false, double, true>(a);
     return launch_apply_t<P, Q, COLLOC, kDiff, false, double>(a);
 }
 

@@ -38,7 +38,10 @@ int validate(const mfhex_desc *d, Basis1D *basis)
     if (d->variable_kappa != 0 && d->variable_kappa != 1) return fail(MFHEX_ERR_ARG, "variable_kappa must be 0 or 1");
     if (d->variable_kappa && d->kind != MFHEX_DIFFUSION)
         return fail(MFHEX_ERR_ARG, "a variable coefficient needs a diffusion operator");
-    if (d->flags & ~(MFHEX_FLAG_F32 | MFHEX_FLAG_RHS)) return fail(MFHEX_ERR_ARG, "unknown flag bits");
+    if (d->flags & ~(MFHEX_FLAG_F32 | MFHEX_FLAG_RHS | MFHEX_FLAG_OTF)) return fail(MFHEX_ERR_ARG, "unknown flag bits");
+    if ((d->flags & MFHEX_FLAG_OTF) &&
+        (d->kind != MFHEX_DIFFUSION || d->variable_kappa || (d->flags & MFHEX_FLAG_F32)))
+        return fail(MFHEX_ERR_UNSUPPORTED, "in-kernel geometric factors: FP64 diffusion with constant kappa only");
     if (!d->vertex_xyz) return fail(MFHEX_ERR_ARG, "vertex_xyz is null");
     const int64_t N = (int64_t)(d->p * (int64_t)d->nex + 1) * (d->p * (int64_t)d->ney + 1) * (d->p * (int64_t)d->nez + 1);
     if (N >= INT32_MAX) return fail(MFHEX_ERR_UNSUPPORTED, "more than 2^31-1 nodes (int32 restriction offsets)");
@@ -63,8 +66,11 @@ Layout workspace_layout(const mfhex_desc &d, int64_t E, int P, int Q)
     o += al(nv * 3 * sizeof(double));
     L.offsets = o;
     o += al(E * P3 * sizeof(int32_t));
-    L.q64 = o;
-    o += al(E * g * Q3 * sizeof(double));
+    L.q64 = SIZE_MAX;
+    if (!(d.flags & MFHEX_FLAG_OTF)) {
+        L.q64 = o;
+        o += al(E * g * Q3 * sizeof(double));
+    }
     L.q32 = SIZE_MAX;
     if (d.flags & MFHEX_FLAG_F32) {
         L.q32 = o;
@@ -141,7 +147,9 @@ bool valid_variant(const mfhex_op_s &op, int prec, int variant)
 {
     if ((prec != MFHEX_F64 && prec != MFHEX_F32) || variant < 0 || variant >= kNumVariants) return false;
     if (variant_vc(variant) > 1 && op.d.variable_kappa) return false;
-    return apply_lds(op.Q, mode_of(op), prec == MFHEX_F32 ? 4 : 8, variant) <= kMaxLds;
+    const bool otf = (op.d.flags & MFHEX_FLAG_OTF) != 0;
+    if (otf && variant_vc(variant) > 1) return false;  // in-kernel factors: single-vector variants
+    return apply_lds(op.Q, mode_of(op), prec == MFHEX_F32 ? 4 : 8, variant, otf) <= kMaxLds;
 }
 
 int default_variant(const mfhex_op_s &op, int prec, int nvec)
@@ -269,6 +277,8 @@ int apply_impl(mfhex_op op, int prec, int nrhs, const void *x, void *y, hipStrea
     a.nvec = nvec;
     a.variant = var;
     a.chain = nchain;
+    a.otf = (op->d.flags & MFHEX_FLAG_OTF) != 0;
+    a.vert = op->vert;
     a.x = x;
     a.y = y;
     a.wdet = nullptr;
@@ -281,6 +291,7 @@ int diagonal_impl(mfhex_op op, double *d, hipStream_t s)
     if (!op) return set_error(nullptr, MFHEX_ERR_ARG, "null handle");
     if (!d) return set_error(op, MFHEX_ERR_ARG, "null output");
     if (op->d.variable_kappa && !op->kappa_set) return set_error(op, MFHEX_ERR_STATE, "kappa not set");
+    if (!op->q64) return set_error(op, MFHEX_ERR_UNSUPPORTED, "the diagonal needs stored geometric factors");
     int c = check_hip(op, hipMemsetAsync(d, 0, op->N * sizeof(double), s), "hipMemsetAsync");
     if (c) return c;
     DiagLaunch a{};
@@ -342,7 +353,7 @@ int mfhex_create(const mfhex_desc *d, void *workspace_dev, size_t workspace_byte
     char *ws = static_cast<char *>(workspace_dev);
     op->vert = reinterpret_cast<double *>(ws + L.vert);
     op->offsets = reinterpret_cast<int32_t *>(ws + L.offsets);
-    op->q64 = reinterpret_cast<double *>(ws + L.q64);
+    op->q64 = L.q64 == SIZE_MAX ? nullptr : reinterpret_cast<double *>(ws + L.q64);
     op->q32 = L.q32 == SIZE_MAX ? nullptr : reinterpret_cast<float *>(ws + L.q32);
     op->kappa = L.kappa == SIZE_MAX ? nullptr : reinterpret_cast<double *>(ws + L.kappa);
     op->wdet = L.wdet == SIZE_MAX ? nullptr : reinterpret_cast<double *>(ws + L.wdet);
@@ -393,6 +404,10 @@ int mfhex_create(const mfhex_desc *d, void *workspace_dev, size_t workspace_byte
         fold(&h[basis_bt(P, Q)], P, Q, &h[basis_btf(P, Q)]);
         fold(&h[basis_d(P, Q)], Q, Q, &h[basis_df(P, Q)]);
         fold(&h[basis_dt(P, Q)], Q, Q, &h[basis_dtf(P, Q)]);
+        for (int a = 0; a < Q; ++a) {
+            h[basis_xq(P, Q) + a] = b.xq[a];
+            h[basis_wq(P, Q) + a] = b.wq[a];
+        }
         for (size_t i = 0; i < h.size(); ++i) h32[i] = (float)h[i];
         if ((c = check_hip(op, hipMemcpy(op->basis64, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice),
                            "copy basis")))

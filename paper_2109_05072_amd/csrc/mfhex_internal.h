@@ -64,6 +64,8 @@ struct ApplyLaunch {
     int nvec;
     int variant;          // launch variant (elements and threads per group)
     int chain;            // mass: element groups per thread group (software pipeline depth), >= 1
+    int otf;              // diffusion FP64: geometric factors evaluated in the kernel from the vertices
+    const double *vert;   // device vertex coordinates [(nex+1)(ney+1)(nez+1)][3] (otf)
     const void *x;        // input (for kRhs: the per-point f, FP64)
     void *y;              // output (accumulated)
     const double *wdet;   // kRhs: w*detJ per point
@@ -123,9 +125,14 @@ constexpr int variant_nt(int Q, int v)
     return v < 5 ? kVarNT[Q - 2][v] : (Q * Q * variant_vc(v) <= 64 ? 64 : Q * Q * variant_vc(v) <= 128 ? 128 : 256);
 }
 // Dynamic LDS bytes of one group of the fused apply.
-constexpr size_t apply_lds(int Q, int mode, int elem_bytes, int v)
+// In-kernel geometric factors: per element its 8 vertices (24 doubles) and
+// the three Jacobian-column tables (3 x Q^2 columns of 3), plus the 1D rule.
+constexpr int otf_lds_doubles(int Q, int G) { return G * (24 + 9 * Q * Q) + 2 * Q; }
+
+constexpr size_t apply_lds(int Q, int mode, int elem_bytes, int v, bool otf = false)
 {
-    return (size_t)variant_g(Q, v, mode) * variant_vc(v) * apply_nbuf(mode) * lds_buf(Q) * elem_bytes;
+    return (size_t)variant_g(Q, v, mode) * variant_vc(v) * apply_nbuf(mode) * lds_buf(Q) * elem_bytes +
+           (otf ? (size_t)otf_lds_doubles(Q, variant_g(Q, v, mode)) * 8 : 0);
 }
 constexpr size_t kMaxLds = 65536;
 
@@ -149,7 +156,9 @@ constexpr int basis_bf(int P, int Q) { return 2 * Q * P + 2 * Q * Q; }
 constexpr int basis_btf(int P, int Q) { return basis_bf(P, Q) + half_up(Q) * P; }
 constexpr int basis_df(int P, int Q) { return basis_btf(P, Q) + half_up(P) * Q; }
 constexpr int basis_dtf(int P, int Q) { return basis_df(P, Q) + half_up(Q) * Q; }
-constexpr int basis_len(int P, int Q) { return basis_dtf(P, Q) + half_up(Q) * Q; }
+constexpr int basis_xq(int P, int Q) { return basis_dtf(P, Q) + half_up(Q) * Q; }  // quadrature points [Q]
+constexpr int basis_wq(int P, int Q) { return basis_xq(P, Q) + Q; }                  // quadrature weights [Q]
+constexpr int basis_len(int P, int Q) { return basis_wq(P, Q) + Q; }
 
 // Per-order dispatch (one translation unit per order, apply_p<N>.hip).
 hipError_t launch_apply(const ApplyLaunch &a);

@@ -1,15 +1,10 @@
 // Setup kernels: quadrature data (geometric factors) and coordinates.
 //
-// Each hexahedron is the trilinear image of [-1,1]^3 through its 8 vertices.
-// The Jacobian columns are written as averages of the element's edge
-// vectors, e.g. dx/dr = 1/8 sum over the four x-edges of
-// (1 +- s)(1 +- t) (X_hi - X_lo); the adjugate rows are the cross products
-// of the columns, so J^{-1} = [ (j_s x j_t); (j_t x j_r); (j_r x j_s) ] / detJ
-// with detJ = j_r . (j_s x j_t).  Stored per point (Sec. 2, the six symmetric
-// geometric factors of A^e = D^T G^e D):
+// Stored per point (Sec. 2, the six symmetric geometric factors of
+// A^e = D^T G^e D; geometry in geom.hpp):
 //   diffusion: G = w adj(J) adj(J)^T / detJ in Voigt order rr, ss, tt, st, rt, rs
 //   mass:      w detJ
-#include "mfhex_internal.h"
+#include "geom.hpp"
 
 namespace mfhex {
 
@@ -20,71 +15,6 @@ struct Rule1D {
     double w[kMaxQ];
 };
 
-struct Elem8 {
-    double X[8][3];  // vertex (dx, dy, dz) at index dx + 2 dy + 4 dz
-};
-
-__device__ __forceinline__ void load_elem(const double *__restrict__ vert, int64_t e, int nex, int ney, Elem8 &el)
-{
-    const int64_t ex = e % nex, ey = (e / nex) % ney, ez = e / ((int64_t)nex * ney);
-    const int64_t vx = nex + 1, vy = ney + 1;
-#pragma unroll
-    for (int v = 0; v < 8; ++v) {
-        const int64_t id = (ex + (v & 1)) + vx * ((ey + ((v >> 1) & 1)) + vy * (ez + ((v >> 2) & 1)));
-#pragma unroll
-        for (int d = 0; d < 3; ++d) el.X[v][d] = vert[3 * id + d];
-    }
-}
-
-__device__ __forceinline__ void map_point(const Elem8 &el, double r, double s, double t, double x[3])
-{
-    const double h[2][3] = {{0.5 * (1 - r), 0.5 * (1 - s), 0.5 * (1 - t)}, {0.5 * (1 + r), 0.5 * (1 + s), 0.5 * (1 + t)}};
-#pragma unroll
-    for (int d = 0; d < 3; ++d) x[d] = 0.0;
-#pragma unroll
-    for (int v = 0; v < 8; ++v) {
-        const double n = h[v & 1][0] * h[(v >> 1) & 1][1] * h[(v >> 2) & 1][2];
-#pragma unroll
-        for (int d = 0; d < 3; ++d) x[d] += n * el.X[v][d];
-    }
-}
-
-// Jacobian columns jr = dx/dr, js = dx/ds, jt = dx/dt from edge vectors.
-__device__ __forceinline__ void jacobian_cols(const Elem8 &el, double r, double s, double t, double jr[3],
-                                              double js[3], double jt[3])
-{
-    const double sm[2] = {1 - s, 1 + s}, tm[2] = {1 - t, 1 + t}, rm[2] = {1 - r, 1 + r};
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-        double ar = 0, as = 0, at = 0;
-#pragma unroll
-        for (int u = 0; u < 2; ++u)
-#pragma unroll
-            for (int w = 0; w < 2; ++w) {
-                // x-edges: vary dx at fixed (dy = u, dz = w)
-                ar += sm[u] * tm[w] * (el.X[1 + 2 * u + 4 * w][d] - el.X[0 + 2 * u + 4 * w][d]);
-                // y-edges: vary dy at fixed (dx = u, dz = w)
-                as += rm[u] * tm[w] * (el.X[u + 2 + 4 * w][d] - el.X[u + 0 + 4 * w][d]);
-                // z-edges: vary dz at fixed (dx = u, dy = w)
-                at += rm[u] * sm[w] * (el.X[u + 2 * w + 4][d] - el.X[u + 2 * w + 0][d]);
-            }
-        jr[d] = 0.125 * ar;
-        js[d] = 0.125 * as;
-        jt[d] = 0.125 * at;
-    }
-}
-
-__device__ __forceinline__ void cross(const double a[3], const double b[3], double c[3])
-{
-    c[0] = a[1] * b[2] - a[2] * b[1];
-    c[1] = a[2] * b[0] - a[0] * b[2];
-    c[2] = a[0] * b[1] - a[1] * b[0];
-}
-
-__device__ __forceinline__ double dot3(const double a[3], const double b[3])
-{
-    return a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
-}
 
 __global__ void k_qdata(int32_t nex, int32_t ney, int32_t nez, int Q, Rule1D rule, const double *__restrict__ vert,
                         int kind, double *__restrict__ q64, float *__restrict__ q32, double *__restrict__ wdet,
@@ -99,18 +29,14 @@ __global__ void k_qdata(int32_t nex, int32_t ney, int32_t nez, int Q, Rule1D rul
     const int a = pt % Q, b = (pt / Q) % Q, c = pt / (Q * Q);
     Elem8 el;
     load_elem(vert, e, nex, ney, el);
-    double jr[3], js[3], jt[3], ar[3], as[3], at[3];
+    double jr[3], js[3], jt[3], g[kQdDiff];
     jacobian_cols(el, rule.x[a], rule.x[b], rule.x[c], jr, js, jt);
-    cross(js, jt, ar);  // adjugate rows
-    cross(jt, jr, as);
-    cross(jr, js, at);
-    const double det = dot3(jr, ar);
     const double w = rule.w[a] * rule.w[b] * rule.w[c];
+    const double det = diffusion_factors(jr, js, jt, w, g);
     if (!(det > 0.0)) atomicOr(bad, 1);
-    if (kind == MFHEX_DIFFUSION) {
-        const double f = w / det;
-        const double g[kQdDiff] = {f * dot3(ar, ar), f * dot3(as, as), f * dot3(at, at),
-                                   f * dot3(as, at), f * dot3(ar, at), f * dot3(ar, as)};
+    if (!q64) {
+        // factors evaluated in the apply kernel: only the Jacobian check (and w detJ)
+    } else if (kind == MFHEX_DIFFUSION) {
         double *o = q64 + e * (kQdDiff * Q3) + pt;
 #pragma unroll
         for (int m = 0; m < kQdDiff; ++m) o[m * Q3] = g[m];

@@ -37,12 +37,14 @@ def kernel_source_hash() -> str:
 
 
 def _short(name: str) -> str:
-    m = re.match(r"void mfhex::k_apply<(\d+), (\d+), (\w+), (\d), (\w+), (\w+), (\d+), (\d+)(?:, (\d+))?>", name)
+    m = re.match(r"void mfhex::k_apply<(\d+), (\d+), (\w+), (\d), (\w+), (\w+), (\d+), (\d+)(?:, (\d+))?"
+                 r"(?:, (true|false))?>", name)
     if m:
-        P, Q, colloc, mode, vark, T, G, NT, VC = m.groups()
+        P, Q, colloc, mode, vark, T, G, NT, VC, otf = m.groups()
         kind = {"0": "mass", "1": "diffusion", "2": "rhs"}[mode]
         vc = f" VC={VC}" if VC and VC != "1" else ""
-        return f"k_apply p={int(P) - 1} q={Q} {kind}{' kappa' if vark == 'true' else ''} {T} G={G} NT={NT}{vc}"
+        geo = " otf" if otf == "true" else ""
+        return f"k_apply p={int(P) - 1} q={Q} {kind}{' kappa' if vark == 'true' else ''}{geo} {T} G={G} NT={NT}{vc}"
     m = re.match(r"void mfhex::k_mass<(\d+), (\d+), (\w+), (\w+), (\d+), (\d+), (\d+)>", name)
     if m:
         P, Q, colloc, T, G, NT, VC = m.groups()

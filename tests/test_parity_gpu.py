@@ -30,10 +30,10 @@ def relerr(a, b):
 
 
 def build(mf, nex, ney, nez, p, kind="diffusion", quad="gauss", dirichlet=True, ncomp=1, vark=False, f32=False,
-          rhs=False, perturb=0.1):
+          rhs=False, perturb=0.1, otf=False):
     vert = synth.mesh_vertices(nex, ney, nez, perturb)
     op = mf.Operator(nex, ney, nez, p, vert, kind=kind, quad=quad, ncomp=ncomp, dirichlet=dirichlet,
-                     variable_kappa=vark, f32=f32, rhs=rhs)
+                     variable_kappa=vark, f32=f32, rhs=rhs, otf=otf)
     q = p + 2 if quad == "gauss" else p + 1
     pr = oracle.Problem(nex, ney, nez, p, q, oracle.GAUSS if quad == "gauss" else oracle.GLL,
                         oracle.DIFFUSION if kind == "diffusion" else oracle.MASS, int(dirichlet), vert)
@@ -369,6 +369,48 @@ def test_cg_solution_and_mixed_precision(gpu_lib, p):
     assert np.abs(x64 - ue).max() < 1e-2
 
 
+# --- geometric factors evaluated in the kernel (no stored factors) ---------------------------
+
+@pytest.mark.parametrize("p", range(1, 9))
+@pytest.mark.parametrize("quad", ["gauss", "gll"])
+@pytest.mark.parametrize("dirichlet", [True, False])
+def test_otf_apply_matches_oracle_and_stored_factors(gpu_lib, p, quad, dirichlet):
+    _say("otf", p, quad, dirichlet)
+    op, pr = build(gpu_lib, 3, 2, 2, p, "diffusion", quad, dirichlet, otf=True)
+    ref, _ = build(gpu_lib, 3, 2, 2, p, "diffusion", quad, dirichlet)
+    x = synth.uniform_vector(pr.n_nodes)
+    yo = oracle.apply(pr, x)
+    ys = host(ref.apply(dev(x)))
+    for v in valid_variants(op):
+        op.set_config(v)
+        ref.set_config(v)
+        _say("otf variant", v, op.get_config())
+        y = host(op.apply(dev(x)))
+        assert relerr(y, yo) <= TOL64
+        # same factor expressions as the set-up kernel: equal to the stored-factor apply up to rounding
+        assert relerr(y, host(ref.apply(dev(x)))) <= 1e-14
+    assert relerr(ys, yo) <= TOL64
+
+
+def test_otf_workspace_has_no_factor_array_and_rejects_what_needs_one(gpu_lib):
+    from paper_2109_05072_amd import _lib as L
+    op, pr = build(gpu_lib, 4, 3, 2, 3, "diffusion", "gauss", True, otf=True)
+    ref, _ = build(gpu_lib, 4, 3, 2, 3, "diffusion", "gauss", True)
+    assert ref.sizes.workspace_bytes - op.sizes.workspace_bytes >= 24 * 6 * 125 * 8
+    with pytest.raises(L.MFHexError) as ei:
+        op.diagonal()
+    assert ei.value.code == L.MFHEX_ERR_UNSUPPORTED
+    for kw in (dict(kind="mass", dirichlet=False), dict(vark=True), dict(f32=True)):
+        with pytest.raises(L.MFHexError) as ei:
+            build(gpu_lib, 2, 2, 2, 2, otf=True, **kw)
+        assert ei.value.code == L.MFHEX_ERR_UNSUPPORTED
+    # the solver runs on it (unpreconditioned)
+    b = dev(synth.uniform_vector(pr.n_nodes, seed=3) * interior_mask(pr))
+    res = op.cg(b, maxit=2000, rtol=1e-10)
+    xo, _, _, _ = oracle.cg(pr, host(b), maxit=2000, rtol=1e-12)
+    assert res.status == 0 and relerr(host(res.x), xo) <= 1e-7
+
+
 # --- operator diagonal and Jacobi-preconditioned CG -----------------------------------------
 
 @pytest.mark.parametrize("p", range(1, 9))
@@ -519,15 +561,17 @@ def _window_value(vert_full, nex, ney, nez, p, quad, kind, dirichlet, x_full, no
 
 
 @pytest.mark.parametrize("p", [3, 4, 5, 6, 7, 8])
-@pytest.mark.parametrize("kind", ["diffusion", "mass"])
+@pytest.mark.parametrize("kind", ["diffusion", "mass", "diffusion-otf"])
 def test_full_size_sampled_against_oracle(gpu_lib, p, kind):
     """The benchmark's operators (about 1e7 nodes, default launch configuration) sampled node by
     node: random nodes, nodes near corners, and nodes on the x-faces inside and between element
     groups (summed on chip before one atomic)."""
     ne = synth.elems_for_dofs(1e7, p)
+    otf = kind == "diffusion-otf"
+    kind = "diffusion" if otf else kind
     dirichlet = kind == "diffusion"
-    _say("full size", p, kind, ne)
-    op, _ = build(gpu_lib, ne, ne, ne, p, kind, "gauss", dirichlet)
+    _say("full size", p, kind, otf, ne)
+    op, _ = build(gpu_lib, ne, ne, ne, p, kind, "gauss", dirichlet, otf=otf)
     _say("launch", op.get_config())
     vert = synth.mesh_vertices(ne, ne, ne)
     x = synth.uniform_vector(op.n_nodes)
