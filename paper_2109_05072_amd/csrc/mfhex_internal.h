@@ -105,11 +105,11 @@ constexpr int apply_nbuf(int mode) { return mode == 1 ? 3 : 1; }
 // writing each node's chunk as one contiguous run.
 constexpr int kNumVariants = 9;
 constexpr int kVarG[9][5] = {
-    {16, 8, 32, 16, 32}, {8, 4, 16, 8, 16}, {4, 2, 8, 4, 8}, {4, 2, 1, 2, 4}, {1, 2, 1, 2, 4},
+    {16, 8, 32, 16, 32}, {8, 4, 16, 8, 16}, {4, 2, 8, 4, 8}, {4, 2, 8, 2, 8}, {1, 2, 1, 2, 4},
     {1, 2, 1, 1, 2},     {1, 1, 1, 2, 2},   {2, 1, 1, 1, 2}, {1, 1, 1, 2, 2}};
 constexpr int kVarNT[9][5] = {
     {64, 64, 64, 128, 128},  {64, 64, 64, 128, 128},  {64, 64, 64, 128, 128},
-    {128, 64, 64, 128, 64},  {64, 64, 128, 128, 128}, {64, 128, 128, 256, 64},
+    {128, 64, 128, 128, 256}, {64, 64, 128, 128, 128}, {64, 128, 128, 256, 64},
     {128, 256, 64, 128, 64}, {256, 128, 64, 128, 256}, {256, 128, 64, 128, 256}};
 constexpr int variant_vc(int v) { return v < 5 ? 1 : v == 5 ? 2 : v == 6 ? 4 : v == 7 ? 8 : 16; }
 // The mass operator keeps one LDS array per element instead of three and has
@@ -140,7 +140,7 @@ constexpr size_t kMaxLds = 65536;
 // mass operator, the pipeline depth measured fastest (median of interleaved
 // timings at about 1e7 DOFs on perturbed box meshes, Gauss q = p+2); orders
 // not measured there keep variant 0.
-constexpr int kDefVariantDiff[9] = {0, 0, 0, 0, 3, 0, 0, 1, 0};
+constexpr int kDefVariantDiff[9] = {0, 0, 0, 4, 3, 0, 0, 1, 0};
 constexpr int kDefVariantMass[9] = {0, 0, 0, 3, 3, 1, 3, 0, 4};
 constexpr int kDefChainMass[9] = {2, 2, 2, 4, 2, 4, 4, 4, 2};
 // Device basis block (elements): B [Q][P], B^T [P][Q], D [Q][Q], D^T [Q][Q],

@@ -24,7 +24,7 @@ import sys
 from collections import defaultdict
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-KERNEL_SOURCES = ("csrc/apply_kernels.hpp", "csrc/mfhex_internal.h")
+KERNEL_SOURCES = ("csrc/apply_kernels.hpp", "csrc/mfhex_internal.h", "csrc/geom.hpp", "csrc/diag_kernels.hpp")
 COPY_BYTES = 1 << 30
 
 
