@@ -14,6 +14,11 @@ paper; these stand in for that suite's structured box meshes):
   fixed, so the domain stays exactly [0,1]^3.  Draws in lexicographic vertex
   order (x fastest), then (dx, dy, dz).
 * vectors: i.i.d. U[-1, 1] in FP64.
+* counter-based U[-1, 1] (``splitmix_uniform``): element i of stream ``seed``
+  is 2 u - 1 with u the top 53 bits of SplitMix64 (Steele, Lea, Flood 2014)
+  applied to seed * 0x632be59bd9b4e019 + i, divided by 2^53.  A draw that a
+  solver makes internally (the start vector of a power iteration) is
+  reproduced exactly from this definition on every side.
 * coefficient: kappa = exp(g), g(x) = sigma sqrt(2/M) sum_k cos(2 pi w_k.x + phi_k),
   w_k ~ N(0, s^2 I_3), phi_k ~ U[0, 2 pi), M = 32, sigma = 0.5, s = 2.
 * manufactured solutions: u = sin(pi x) sin(pi y) sin(pi z) with
@@ -54,6 +59,20 @@ def uniform_vector(n: int, nvec: int = 1, seed: int = SEED_VEC) -> np.ndarray:
     rng = np.random.default_rng(seed)
     x = rng.uniform(-1.0, 1.0, size=(n, nvec))
     return np.ascontiguousarray(x[:, 0] if nvec == 1 else x)
+
+
+_MASK64 = (1 << 64) - 1
+
+
+def splitmix_uniform(n: int, seed: int) -> np.ndarray:
+    """Counter-based U[-1, 1] float64 [n]: element i from SplitMix64 of seed*0x632be59bd9b4e019 + i."""
+    with np.errstate(over="ignore"):
+        z = (np.uint64((seed * 0x632BE59BD9B4E019) & _MASK64) + np.arange(n, dtype=np.uint64))
+        z = z + np.uint64(0x9E3779B97F4A7C15)
+        z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+        z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+        z = z ^ (z >> np.uint64(31))
+    return 2.0 * ((z >> np.uint64(11)).astype(np.float64) * (1.0 / 9007199254740992.0)) - 1.0
 
 
 def kappa_modes(nmodes: int = 32, sigma: float = 0.5, scale: float = 2.0, seed: int = SEED_KAPPA):

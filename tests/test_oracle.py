@@ -403,3 +403,98 @@ def test_jacobi_cuts_iterations_for_a_high_contrast_coefficient():
     _, _, it_pcg, c2 = oracle.pcg(pr, b, oracle.jacobi_inverse(oracle.diagonal(pr)), maxit=5000, rtol=1e-10)
     assert c1 == oracle.OK and c2 == oracle.OK
     assert it_pcg < 0.5 * it_cg
+
+
+# --- p-multigrid (oracle) -------------------------------------------------------------------
+
+def test_splitmix_uniform_follows_the_published_definition():
+    # SplitMix64 (Steele, Lea, Flood 2014): from state 1234567 the first output is
+    # 6457827717110365317; the vectorized generator must agree with plain integer arithmetic
+    M = (1 << 64) - 1
+
+    def mix(z):
+        z = (z + 0x9E3779B97F4A7C15) & M
+        z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & M
+        z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & M
+        return z ^ (z >> 31)
+
+    assert mix(1234567) == 6457827717110365317
+    seed = 99
+    v = synth.splitmix_uniform(7, seed)
+    for i in range(7):
+        z = mix((seed * 0x632BE59BD9B4E019 + i) & M)
+        assert v[i] == 2.0 * ((z >> 11) / 9007199254740992.0) - 1.0
+
+
+def test_prolongation_reproduces_coarse_polynomials_on_affine_meshes():
+    # unperturbed mesh: a polynomial of degree <= p_c in each variable lies in the coarse space,
+    # so its coarse nodal values prolong to its values at the fine nodes (interpolation exactness)
+    from oracle import multigrid as mg
+    for pc, pf in [(1, 2), (1, 3), (2, 4), (2, 5), (3, 6), (4, 8)]:
+        prf = _prob(2, pf, oracle.DIFFUSION, perturb=0.0)
+        prc = mg.level_problem(prf, pc)
+        P = mg.prolongation(prc, prf)
+        f = lambda X: X[:, 0] ** pc * (1 + X[:, 1]) + X[:, 2] ** pc - 2 * X[:, 0] * X[:, 1] * X[:, 2] ** (pc - 1)
+        xc = f(oracle.node_coords(prc))
+        np.testing.assert_allclose(P @ xc, f(oracle.node_coords(prf)), atol=1e-13)
+        # partition of unity on the perturbed mesh too (no mask)
+        prf2 = _prob(2, pf, oracle.DIFFUSION)
+        P2 = mg.prolongation(mg.level_problem(prf2, pc), prf2)
+        np.testing.assert_allclose(P2 @ np.ones(P2.shape[1]), 1.0, atol=1e-13)
+
+
+def test_chebyshev_meets_its_error_bound():
+    # with the exact extreme eigenvalues of D^-1 A (dense generalized eigenproblem on a tiny
+    # mesh), k Chebyshev steps reduce the A-norm error by at most 2 c^k / (1 + c^2k),
+    # c = (sqrt(kappa) - 1) / (sqrt(kappa) + 1) -- the textbook minimax bound
+    import scipy.linalg as sla
+    from oracle import multigrid as mg
+    pr = _prob(2, 2, oracle.DIFFUSION, dirichlet=1)
+    inner = _interior(pr)
+    A = oracle.apply(pr, np.eye(pr.n_nodes))[np.ix_(inner, inner)]
+    d = oracle.diagonal(pr)
+    dinv = oracle.jacobi_inverse(d)
+    ev = sla.eigh(A, np.diag(d[inner]), eigvals_only=True)
+    lo, hi = ev[0], ev[-1]
+    b = synth.uniform_vector(pr.n_nodes) * inner
+    xs = np.zeros(pr.n_nodes)
+    xs[inner] = np.linalg.solve(A, b[inner])
+    kap = hi / lo
+    c = (np.sqrt(kap) - 1) / (np.sqrt(kap) + 1)
+    e0 = np.sqrt(xs[inner] @ A @ xs[inner])
+    for k in (1, 2, 4, 8, 16):
+        x = mg.chebyshev(pr, dinv, lo, hi, b, np.zeros(pr.n_nodes), k)
+        e = xs[inner] - x[inner]
+        assert np.sqrt(e @ A @ e) <= 2 * c ** k / (1 + c ** (2 * k)) * e0 * (1 + 1e-10)
+
+
+def test_power_method_brackets_the_top_eigenvalue():
+    import scipy.linalg as sla
+    from oracle import multigrid as mg
+    pr = _prob(2, 3, oracle.DIFFUSION, dirichlet=1)
+    inner = _interior(pr)
+    A = oracle.apply(pr, np.eye(pr.n_nodes))[np.ix_(inner, inner)]
+    d = oracle.diagonal(pr)
+    top = sla.eigh(A, np.diag(d[inner]), eigvals_only=True)[-1]
+    lam = mg.lambda_max(pr, oracle.jacobi_inverse(d), 15, 2024)
+    assert 0.85 * top <= lam <= top * (1 + 1e-12)
+
+
+def test_vcycle_is_a_symmetric_positive_preconditioner_and_mg_pcg_solves():
+    from oracle import multigrid as mg
+    pr = _prob(3, 4, oracle.DIFFUSION, dirichlet=1)
+    h = mg.Hierarchy(pr)
+    assert [L["pr"].p for L in h.levels] == [4, 2, 1]
+    inner = _interior(pr)
+    u = synth.uniform_vector(pr.n_nodes, seed=1) * inner
+    v = synth.uniform_vector(pr.n_nodes, seed=2) * inner
+    Mu, Mv = h.vcycle(u), h.vcycle(v)
+    # symmetric (R = P^T, equal pre- and post-smoothers) and positive definite
+    assert abs(u @ Mv - v @ Mu) <= 1e-12 * abs(u @ Mv)
+    assert u @ Mu > 0 and v @ Mv > 0
+    b = synth.uniform_vector(pr.n_nodes, seed=3) * inner
+    x, hist, it = mg.mg_pcg(h, b, maxit=200, rtol=1e-10)
+    xs = spla.spsolve(oracle.assemble(pr)[inner][:, inner], b[inner])
+    assert np.abs(x[inner] - xs).max() < 1e-8 * np.abs(xs).max()
+    _, _, it_j, _ = oracle.pcg(pr, b, oracle.jacobi_inverse(oracle.diagonal(pr)), maxit=2000, rtol=1e-10)
+    assert it < 0.3 * it_j
