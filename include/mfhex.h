@@ -59,7 +59,7 @@ enum { MFHEX_MASS = 1, MFHEX_DIFFUSION = 2 };      /* operator kind       */
 enum { MFHEX_GAUSS = 0, MFHEX_GLL = 1 };           /* quadrature rule     */
 enum { MFHEX_F64 = 0, MFHEX_F32 = 1 };             /* arithmetic / data   */
 enum { MFHEX_CG_F64 = 0, MFHEX_CG_MIXED = 1 };     /* solver mode         */
-enum { MFHEX_PRECOND_NONE = 0, MFHEX_PRECOND_JACOBI = 1 }; /* CG preconditioner */
+enum { MFHEX_PRECOND_NONE = 0, MFHEX_PRECOND_JACOBI = 1, MFHEX_PRECOND_MG = 2 }; /* CG preconditioner */
 
 /* desc.flags bits */
 #define MFHEX_FLAG_F32 1u  /* also build FP32 quadrature data (for prec = MFHEX_F32) */
@@ -177,7 +177,8 @@ int mfhex_rhs(mfhex_op op, const double *f_dev, double *b_dev, void *stream);
  *   precond MFHEX_PRECOND_JACOBI: Jacobi-preconditioned CG in either mode,
  *   z = D^-1 r with D = mfhex_diagonal (computed and inverted at the start of
  *   every solve; 0 at masked nodes), alpha = r.z / p.Ap, beta from r.z; the
- *   stopping test stays on ||r||.  pad_ must be 0. */
+ *   stopping test stays on ||r||.  precond MFHEX_PRECOND_MG: one p-multigrid
+ *   V-cycle per iteration (mfhex_mg_setup first; FP64 mode only).  pad_ must be 0. */
 typedef struct {
     int32_t maxit, check_every, mode, replace_every, x0_is_zero, max_iters_exact, precond, pad_;
     double rtol, replace_delta;
@@ -201,6 +202,42 @@ typedef struct {
  * solvers of Sec. 2.) */
 int mfhex_cg(mfhex_op op, const double *b_dev, double *x_dev, void *cg_work_dev, const mfhex_cg_opts *opts,
              mfhex_cg_stats *stats, double *rhist, void *stream);
+
+/* p-multigrid preconditioner (Sec. 1: p-multigrid in high-order codes;
+ * Sec. 2, Nek5000/RS: Chebyshev-accelerated Jacobi smoothing).  Levels p,
+ * floor(p/2), ..., 1 on the operator's mesh (same quadrature family and
+ * mask); prolongation = the coarse field at the fine nodes, restriction its
+ * transpose; on every level a Chebyshev smoother on D^-1 A (D =
+ * mfhex_diagonal) over [lo, hi] x lambda, lambda from power_iters steps of
+ * the power method (start vector: SplitMix64 uniform, seed 2024, masked; the
+ * generalized Rayleigh quotient of the last iterate); V-cycle: pre-smooth
+ * from 0 (degree), restrict, recurse, prolong and add, post-smooth (degree);
+ * the coarsest level is smoothed only (coarse_degree).  Fields left 0 take
+ * the defaults degree 3, coarse_degree 8, power_iters 15, all levels,
+ * lo 0.25, hi 1.1.  Scalar FP64 diffusion with stored factors and constant
+ * kappa only. */
+typedef struct {
+    int32_t degree, coarse_degree, power_iters, max_levels;
+    double lo, hi;
+} mfhex_mg_opts;
+
+/* Device work-area size (bytes, 256-byte aligned buffer) and level count for
+ * a hierarchy on an operator of description `fine` (opts may be NULL). */
+int mfhex_mg_query(const mfhex_desc *fine, const mfhex_mg_opts *opts, size_t *work_bytes, int32_t *nlevels);
+
+/* Build the hierarchy and attach it to `op` (created from `fine`, whose
+ * vertex pointer is read again for the coarse levels).  work_dev:
+ * caller-owned device buffer of mfhex_mg_query's size; it holds the coarse
+ * operators, level vectors and transfer matrices and must outlive `op`
+ * (mfhex_destroy releases the coarse handles).  Synchronizes `stream`. */
+int mfhex_mg_setup(mfhex_op op, const mfhex_desc *fine, const mfhex_mg_opts *opts, void *work_dev, size_t work_bytes,
+                   void *stream);
+
+/* z = M^-1 r: one V-cycle.  r, z: device FP64 [n_nodes], distinct.  Asynchronous. */
+int mfhex_mg_apply(mfhex_op op, const double *r_dev, double *z_dev, void *stream);
+
+/* Order, node count and lambda_max(D^-1 A) estimate of level `level` (0 = finest). */
+int mfhex_mg_level(mfhex_op op, int level, int32_t *p, int64_t *n_nodes, double *lambda_max);
 
 /* Autotune the apply for (prec, nrhs): time every launch variant of the
  * fused kernel (elements per thread group, threads per group; for the mass

@@ -25,14 +25,15 @@ MFHEX_MASS, MFHEX_DIFFUSION = 1, 2
 MFHEX_GAUSS, MFHEX_GLL = 0, 1
 MFHEX_F64, MFHEX_F32 = 0, 1
 MFHEX_CG_F64, MFHEX_CG_MIXED = 0, 1
-MFHEX_PRECOND_NONE, MFHEX_PRECOND_JACOBI = 0, 1
+MFHEX_PRECOND_NONE, MFHEX_PRECOND_JACOBI, MFHEX_PRECOND_MG = 0, 1, 2
 MFHEX_FLAG_F32, MFHEX_FLAG_RHS, MFHEX_FLAG_OTF = 1, 2, 4
 
 # every symbol include/mfhex.h declares
 EXPORTS = (
     "mfhex_query", "mfhex_create", "mfhex_destroy", "mfhex_set_kappa", "mfhex_apply", "mfhex_apply_add",
     "mfhex_apply_adjoint", "mfhex_kappa_grad", "mfhex_qpoint_coords", "mfhex_node_coords", "mfhex_rhs",
-    "mfhex_cg", "mfhex_tune", "mfhex_get_config", "mfhex_set_config", "mfhex_diagonal", "mfhex_strerror", "mfhex_last_error",
+    "mfhex_cg", "mfhex_tune", "mfhex_get_config", "mfhex_set_config", "mfhex_diagonal", "mfhex_mg_query", "mfhex_mg_setup",
+    "mfhex_mg_apply", "mfhex_mg_level", "mfhex_strerror", "mfhex_last_error",
     "mfhex_basis_1d", "mfhex_version",
 )
 
@@ -58,6 +59,11 @@ class mfhex_cg_opts(C.Structure):
     _fields_ = [("maxit", C.c_int32), ("check_every", C.c_int32), ("mode", C.c_int32),
                 ("replace_every", C.c_int32), ("x0_is_zero", C.c_int32), ("max_iters_exact", C.c_int32),
                 ("precond", C.c_int32), ("pad_", C.c_int32), ("rtol", C.c_double), ("replace_delta", C.c_double)]
+
+
+class mfhex_mg_opts(C.Structure):
+    _fields_ = [("degree", C.c_int32), ("coarse_degree", C.c_int32), ("power_iters", C.c_int32),
+                ("max_levels", C.c_int32), ("lo", C.c_double), ("hi", C.c_double)]
 
 
 class mfhex_cg_stats(C.Structure):
@@ -104,6 +110,10 @@ def load(path: str = LIB_PATH):
         "mfhex_tune": ([vp, i32, i32, vp, C.c_char_p, vp], i32),
         "mfhex_get_config": ([vp, i32, i32, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                               C.POINTER(C.c_int32), C.POINTER(C.c_int32)], i32),
+        "mfhex_mg_query": ([C.POINTER(mfhex_desc), C.POINTER(mfhex_mg_opts), C.POINTER(sz), C.POINTER(C.c_int32)], i32),
+        "mfhex_mg_setup": ([vp, C.POINTER(mfhex_desc), C.POINTER(mfhex_mg_opts), vp, sz, vp], i32),
+        "mfhex_mg_apply": ([vp, vp, vp, vp], i32),
+        "mfhex_mg_level": ([vp, i32, C.POINTER(C.c_int32), C.POINTER(C.c_int64), C.POINTER(C.c_double)], i32),
         "mfhex_diagonal": ([vp, vp, vp], i32),
         "mfhex_set_config": ([vp, i32, i32, C.c_int32, C.c_int32], i32),
         "mfhex_strerror": ([i32], C.c_char_p),
@@ -204,6 +214,28 @@ def mfhex_set_config(op: int, prec: int, nrhs: int, variant: int, groups_per_blo
 
 def mfhex_diagonal(op: int, d: int, stream: int) -> None:
     check(load().mfhex_diagonal(op, d, stream), op)
+
+
+def mfhex_mg_query(d: mfhex_desc, opts: mfhex_mg_opts):
+    """(work bytes, number of levels) of a p-multigrid hierarchy."""
+    nb, nl = C.c_size_t(), C.c_int32()
+    check(load().mfhex_mg_query(C.byref(d), C.byref(opts), C.byref(nb), C.byref(nl)), None)
+    return nb.value, nl.value
+
+
+def mfhex_mg_setup(op: int, d: mfhex_desc, opts: mfhex_mg_opts, work: int, nbytes: int, stream: int) -> None:
+    check(load().mfhex_mg_setup(op, C.byref(d), C.byref(opts), work, nbytes, stream), op)
+
+
+def mfhex_mg_apply(op: int, r: int, z: int, stream: int) -> None:
+    check(load().mfhex_mg_apply(op, r, z, stream), op)
+
+
+def mfhex_mg_level(op: int, level: int):
+    """(order, nodes, lambda_max estimate) of a level (0 = finest)."""
+    p, n, lam = C.c_int32(), C.c_int64(), C.c_double()
+    check(load().mfhex_mg_level(op, level, C.byref(p), C.byref(n), C.byref(lam)), op)
+    return p.value, n.value, lam.value
 
 
 def mfhex_strerror(code: int) -> str:

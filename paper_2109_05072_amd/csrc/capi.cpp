@@ -55,6 +55,12 @@ int validate(const mfhex_desc *d, Basis1D *basis)
 
 namespace mfhex {
 
+int fail_global(int code, const std::string &msg) { return fail(code, msg); }
+
+}  // namespace mfhex
+
+namespace mfhex {
+
 Layout workspace_layout(const mfhex_desc &d, int64_t E, int P, int Q)
 {
     const int g = d.kind == MFHEX_DIFFUSION ? kQdDiff : 1;
@@ -440,6 +446,7 @@ int mfhex_create(const mfhex_desc *d, void *workspace_dev, size_t workspace_byte
 int mfhex_destroy(mfhex_op op)
 {
     if (!op) return MFHEX_OK;
+    mg_release(op);
     if (op->pinned) (void)hipHostFree(op->pinned);
     delete op;
     return MFHEX_OK;

@@ -42,7 +42,8 @@ struct Ctx {
     int64_t n;
     double *r64, *p64, *ap64, *partial, *sc, *hist;
     float *r32, *p32, *ap32;
-    bool pre;  // Jacobi preconditioning
+    bool pre;  // preconditioned (Jacobi or multigrid)
+    bool mg;   // multigrid V-cycle as the preconditioner
     double *z64, *dinv64;
     float *z32, *dinv32;
 };
@@ -69,11 +70,16 @@ int dot_store(Ctx &ctx, const void *a, int pa, const void *b, int pb, int slot)
     return MFHEX_OK;
 }
 
-// z = dinv r and r.z into sc[slot] (prec: of r, z and dinv).
+// z = M^-1 r (Jacobi: dinv r; multigrid: one V-cycle, FP64) and r.z into sc[slot].
 int precond_store(Ctx &ctx, int prec, const void *r, void *z, int slot)
 {
-    const void *dinv = prec == MFHEX_F64 ? (const void *)ctx.dinv64 : (const void *)ctx.dinv32;
-    HIP(launch_precond(r, dinv, z, prec, ctx.n, ctx.partial, ctx.s), "preconditioner kernel");
+    if (ctx.mg) {
+        TRY(mg_vcycle(ctx.op, static_cast<const double *>(r), static_cast<double *>(z), ctx.s));
+        HIP(launch_dot(r, MFHEX_F64, z, MFHEX_F64, ctx.n, ctx.partial, ctx.s), "dot kernel");
+    } else {
+        const void *dinv = prec == MFHEX_F64 ? (const void *)ctx.dinv64 : (const void *)ctx.dinv32;
+        HIP(launch_precond(r, dinv, z, prec, ctx.n, ctx.partial, ctx.s), "preconditioner kernel");
+    }
     HIP(launch_finalize(ctx.partial, ctx.sc, kFinStore, slot, nullptr, 0, ctx.s), "finalize kernel");
     return MFHEX_OK;
 }
@@ -112,7 +118,13 @@ int cg64(Ctx &ctx, const double *b, double *x, const mfhex_cg_opts &o, bool x0_z
         HIP(launch_dot(ctx.p64, MFHEX_F64, ctx.ap64, MFHEX_F64, n, ctx.partial, ctx.s), "dot kernel");
         HIP(launch_finalize(ctx.partial, ctx.sc, ctx.pre ? kFinAlphaPre : kFinAlpha, 0, nullptr, 0, ctx.s),
             "finalize kernel");
-        if (ctx.pre)
+        if (ctx.mg) {
+            // r.r from the update, then z = V(r) and r.z into the second half of the partials
+            HIP(launch_update_xr(x, ctx.r64, ctx.p64, ctx.ap64, MFHEX_F64, ctx.sc, n, ctx.partial, ctx.s),
+                "update kernel");
+            TRY(mg_vcycle(ctx.op, ctx.r64, ctx.z64, ctx.s));
+            HIP(launch_dot(ctx.r64, MFHEX_F64, ctx.z64, MFHEX_F64, n, ctx.partial + kRedBlocks, ctx.s), "dot kernel");
+        } else if (ctx.pre)
             HIP(launch_update_xrz(x, ctx.r64, ctx.p64, ctx.ap64, ctx.dinv64, ctx.z64, MFHEX_F64, ctx.sc, n, ctx.partial,
                                   ctx.s),
                 "update kernel");
@@ -177,8 +189,12 @@ int cg_solve(mfhex_op op, const double *b, double *x, void *work, const mfhex_cg
     if (op->d.ncomp != 1) return set_error(op, MFHEX_ERR_UNSUPPORTED, "CG solves one component (ncomp = 1)");
     if (o->maxit < 0 || !(o->rtol >= 0.0)) return set_error(op, MFHEX_ERR_ARG, "bad maxit or rtol");
     if (o->mode != MFHEX_CG_F64 && o->mode != MFHEX_CG_MIXED) return set_error(op, MFHEX_ERR_ARG, "bad CG mode");
-    if (o->precond != MFHEX_PRECOND_NONE && o->precond != MFHEX_PRECOND_JACOBI)
+    if (o->precond != MFHEX_PRECOND_NONE && o->precond != MFHEX_PRECOND_JACOBI && o->precond != MFHEX_PRECOND_MG)
         return set_error(op, MFHEX_ERR_ARG, "bad preconditioner");
+    if (o->precond == MFHEX_PRECOND_MG && !op->mg)
+        return set_error(op, MFHEX_ERR_STATE, "multigrid preconditioner needs mfhex_mg_setup");
+    if (o->precond == MFHEX_PRECOND_MG && o->mode != MFHEX_CG_F64)
+        return set_error(op, MFHEX_ERR_UNSUPPORTED, "multigrid preconditioning runs in FP64 mode");
     if (o->mode == MFHEX_CG_MIXED && !op->q32)
         return set_error(op, MFHEX_ERR_STATE, "mixed CG needs an operator created with MFHEX_FLAG_F32");
     if (o->mode == MFHEX_CG_MIXED && op->d.variable_kappa)
@@ -192,11 +208,11 @@ int cg_solve(mfhex_op op, const double *b, double *x, void *work, const mfhex_cg
             reinterpret_cast<double *>(w + L.ap64), reinterpret_cast<double *>(w + L.partial),
             reinterpret_cast<double *>(w + L.sc), reinterpret_cast<double *>(w + L.hist),
             reinterpret_cast<float *>(w + L.r32), reinterpret_cast<float *>(w + L.p32),
-            reinterpret_cast<float *>(w + L.ap32), o->precond == MFHEX_PRECOND_JACOBI,
+            reinterpret_cast<float *>(w + L.ap32), o->precond != MFHEX_PRECOND_NONE, o->precond == MFHEX_PRECOND_MG,
             reinterpret_cast<double *>(w + L.z64), reinterpret_cast<double *>(w + L.dinv64),
             reinterpret_cast<float *>(w + L.z32), reinterpret_cast<float *>(w + L.dinv32)};
     HIP(hipMemsetAsync(ctx.sc, 0, kNumSc * sizeof(double), s), "hipMemsetAsync");
-    if (ctx.pre) {
+    if (ctx.pre && !ctx.mg) {
         // operator diagonal into dinv64, inverted in place (FP32 copy for mixed mode)
         TRY(diagonal_impl(op, ctx.dinv64, s));
         HIP(launch_jacobi_inverse(ctx.dinv64, ctx.dinv64, ctx.dinv32, op->N, s), "inverse kernel");

@@ -2,10 +2,12 @@
 #pragma once
 
 #include <map>
+#include <memory>
 #include <string>
 #include <utility>
 
 #include "mfhex_internal.h"
+#include "mg.h"
 
 struct mfhex_op_s {
     mfhex_desc d{};           // copy of the description (vertex pointer cleared)
@@ -25,6 +27,7 @@ struct mfhex_op_s {
     float *basis32 = nullptr;
     bool kappa_set = false;
     std::map<std::pair<int, int>, mfhex::LaunchCfg> config;  // (prec, nvec) -> apply launch configuration
+    std::unique_ptr<mfhex::MgHierarchy> mg;                  // p-multigrid levels (mfhex_mg_setup)
     std::string err;
     double *pinned = nullptr;  // small pinned host buffer for solver scalars
 };
@@ -45,6 +48,10 @@ constexpr int kHist = 8192;
 CgLayout cg_layout(int64_t n);
 
 int set_error(mfhex_op op, int code, const std::string &msg);
+int fail_global(int code, const std::string &msg);  // failure of a call without a handle
+// p-multigrid: one V-cycle z = M^-1 r on the fine operator; release of the hierarchy.
+int mg_vcycle(mfhex_op op, const double *r, double *z, hipStream_t s);
+void mg_release(mfhex_op op);
 int check_hip(mfhex_op op, hipError_t e, const char *what);
 
 // Internal apply: y (+)= A x on `s` with an explicit configuration.

@@ -169,25 +169,55 @@ class Operator:
     def cg(self, b: torch.Tensor, x: Optional[torch.Tensor] = None, maxit: int = 1000, rtol: float = 1e-10,
            mode: str = "f64", check_every: int = 1, replace_every: int = 100, replace_delta: float = 0.1,
            exact_iters: bool = False, precond: str = "none") -> CGResult:
-        """Solve A x = b by CG: mode "f64" or "mixed" (reliable updates), precond "none" or "jacobi"."""
+        """Solve A x = b by CG: mode "f64" or "mixed" (reliable updates), precond "none", "jacobi" or "mg"
+        (one p-multigrid V-cycle per iteration; mg_setup first, FP64 mode)."""
         self._check_vec(b, 1)
         if self._cg_work is None:
             self._cg_work = torch.empty(int(self.sizes.cg_work_bytes) + 256, dtype=torch.uint8, device=self.device)
         work = (self._cg_work.data_ptr() + 255) & ~255
         x0_zero = x is None
         x = torch.zeros_like(b) if x is None else x
-        if precond not in ("none", "jacobi"):
+        if precond not in ("none", "jacobi", "mg"):
             raise ValueError(f"unknown preconditioner {precond!r}")
         opts = L.mfhex_cg_opts(maxit=maxit, check_every=check_every,
                                mode=L.MFHEX_CG_MIXED if mode == "mixed" else L.MFHEX_CG_F64,
                                replace_every=replace_every, x0_is_zero=int(x0_zero), max_iters_exact=int(exact_iters),
-                               precond=L.MFHEX_PRECOND_JACOBI if precond == "jacobi" else L.MFHEX_PRECOND_NONE,
+                               precond={"none": L.MFHEX_PRECOND_NONE, "jacobi": L.MFHEX_PRECOND_JACOBI,
+                                        "mg": L.MFHEX_PRECOND_MG}[precond],
                                rtol=rtol, replace_delta=replace_delta)
         hist = np.zeros(min(maxit, 8191) + 1)
         code, st = L.mfhex_cg(self.handle, b.data_ptr(), x.data_ptr(), work, opts,
                               hist.ctypes.data_as(C.POINTER(C.c_double)), _stream())
         return CGResult(x, code, st.iters, st.replacements, bool(st.fell_back_to_f64), st.rel_resid_true,
                         st.rel_resid_rec, st.seconds, hist[: min(st.iters, 8191) + 1])
+
+    # -- p-multigrid -------------------------------------------------------------------------
+    def mg_setup(self, degree: int = 0, coarse_degree: int = 0, power_iters: int = 0, max_levels: int = 0,
+                 lo: float = 0.0, hi: float = 0.0) -> int:
+        """Build the p-multigrid hierarchy (levels p, p/2, ..., 1); 0 keeps a default.  Returns the level count."""
+        opts = L.mfhex_mg_opts(degree, coarse_degree, power_iters, max_levels, lo, hi)
+        nbytes, nl = L.mfhex_mg_query(self.desc, opts)
+        self._mg_work = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        ptr = (self._mg_work.data_ptr() + 255) & ~255
+        L.mfhex_mg_setup(self.handle, self.desc, opts, ptr, nbytes, _stream())
+        return nl
+
+    def mg_apply(self, r: torch.Tensor, z: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """z = M^-1 r, one V-cycle."""
+        self._check_vec(r, 1)
+        z = torch.empty_like(r) if z is None else z
+        L.mfhex_mg_apply(self.handle, r.data_ptr(), z.data_ptr(), _stream())
+        return z
+
+    def mg_levels(self):
+        """[(order, nodes, lambda_max estimate)] from the finest level down."""
+        out, lvl = [], 0
+        while True:
+            try:
+                out.append(L.mfhex_mg_level(self.handle, lvl))
+            except L.MFHexError:
+                return out
+            lvl += 1
 
     # -- tuning ------------------------------------------------------------------------------
     def tune(self, dtype=torch.float64, nrhs: int = 1, cache_path: Optional[str] = None):

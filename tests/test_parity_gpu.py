@@ -502,6 +502,68 @@ def test_pcg_rejects_unknown_preconditioner(gpu_lib):
     assert ei.value.code == L.MFHEX_ERR_ARG
 
 
+# --- p-multigrid preconditioner -------------------------------------------------------------
+
+@pytest.mark.parametrize("p,quad", [(2, "gauss"), (3, "gauss"), (4, "gauss"), (5, "gauss"), (6, "gauss"),
+                                    (7, "gauss"), (8, "gauss"), (4, "gll"), (7, "gll")])
+def test_mg_levels_and_vcycle_match_oracle(gpu_lib, p, quad):
+    from oracle import multigrid as omg
+    _say("mg vcycle", p, quad)
+    op, pr = build(gpu_lib, 3, 2, 2, p, "diffusion", quad, True)
+    nl = op.mg_setup()
+    h = omg.Hierarchy(pr)
+    lv = op.mg_levels()
+    assert nl == len(lv) == len(h.levels)
+    for (pl, nl_nodes, lam), L in zip(lv, h.levels):
+        assert pl == L["pr"].p and nl_nodes == L["pr"].n_nodes
+        assert abs(lam - L["lam"]) <= 1e-10 * L["lam"]
+    r = synth.uniform_vector(pr.n_nodes, seed=5) * interior_mask(pr)
+    z = host(op.mg_apply(dev(r)))
+    zo = h.vcycle(r)
+    print("vcycle rel diff", relerr(z, zo))
+    assert relerr(z, zo) <= 1e-9
+    # symmetric preconditioner: u.M v == v.M u
+    u = synth.uniform_vector(pr.n_nodes, seed=6) * interior_mask(pr)
+    zu = host(op.mg_apply(dev(u)))
+    assert abs(u @ z - r @ zu) <= 1e-11 * abs(u @ z)
+
+
+@pytest.mark.parametrize("p,ne", [(3, 8), (5, 5), (8, 3)])
+def test_mg_pcg_matches_oracle(gpu_lib, p, ne):
+    from oracle import multigrid as omg
+    op, pr = build(gpu_lib, ne, ne, ne, p, "diffusion", "gauss", True, rhs=True)
+    op.mg_setup()
+    b = _masked_rhs(op, pr)
+    res = op.cg(b, maxit=500, rtol=1e-10, precond="mg")
+    rj = op.cg(b, maxit=5000, rtol=1e-10, precond="jacobi")
+    bo = oracle.rhs(pr, synth.sin_forcing(oracle.qpoint_geometry(pr)[0]))
+    xo, ho, it_o = omg.mg_pcg(omg.Hierarchy(pr), bo, maxit=500, rtol=1e-10)
+    print("mg pcg", p, ne, "iters", res.iters, "oracle", it_o, "jacobi", rj.iters)
+    assert res.status == 0 and res.rel_resid_true <= 1e-10
+    assert abs(res.iters - it_o) <= 2
+    assert res.iters < 0.3 * rj.iters
+    assert relerr(host(res.x), xo) <= 1e-7
+
+
+def test_mg_rejects_what_it_does_not_support(gpu_lib):
+    from paper_2109_05072_amd import _lib as L
+    op, pr = build(gpu_lib, 2, 2, 2, 2)
+    b = dev(synth.uniform_vector(pr.n_nodes) * interior_mask(pr))
+    with pytest.raises(L.MFHexError) as ei:
+        op.cg(b, precond="mg")  # no hierarchy yet
+    assert ei.value.code == L.MFHEX_ERR_STATE
+    for kw in (dict(kind="mass", dirichlet=False), dict(otf=True), dict(vark=True)):
+        o2, _ = build(gpu_lib, 2, 2, 2, 2, **kw)
+        with pytest.raises(L.MFHexError) as ei:
+            o2.mg_setup()
+        assert ei.value.code == L.MFHEX_ERR_UNSUPPORTED
+    o3, _ = build(gpu_lib, 2, 2, 2, 3, f32=True)
+    o3.mg_setup()
+    with pytest.raises(L.MFHexError) as ei:
+        o3.cg(dev(synth.uniform_vector(o3.n_nodes) * interior_mask(pr.with_(p=3, q=5))), mode="mixed", precond="mg")
+    assert ei.value.code == L.MFHEX_ERR_UNSUPPORTED
+
+
 # --- error paths -----------------------------------------------------------------------------
 
 def test_error_paths(gpu_lib):
