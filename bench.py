@@ -387,6 +387,12 @@ def cg_compare(orders=(3, 5, 7), dofs=3e7):
         torch.cuda.synchronize()
         mg_setup_s = time.perf_counter() - t0
         rmg = op.cg(b, maxit=2000, rtol=1e-10, mode="f64", precond="mg")
+        mg_lv = [lv[0] for lv in op.mg_levels()]
+        t0 = time.perf_counter()
+        op.mg_setup(dtype=torch.float32)
+        torch.cuda.synchronize()
+        mg32_setup_s = time.perf_counter() - t0
+        rmg32 = op.cg(b, maxit=2000, rtol=1e-10, mode="f64", precond="mg")
         d = float((rmx.x - r64.x).norm() / r64.x.norm())
         ue = torch.from_numpy(synth.sin_solution(op.node_coords().cpu().numpy())).cuda()
         res.append({"p": p, "dofs": op.n_nodes, "f64_s": round(r64.seconds, 4), "f64_iters": r64.iters,
@@ -402,11 +408,15 @@ def cg_compare(orders=(3, 5, 7), dofs=3e7):
                     "jacobi_mixed_rel_resid": jmx.rel_resid_true,
                     "jacobi_rel_diff_x_vs_f64": float((j64.x - r64.x).norm() / r64.x.norm()),
                     "speedup_jacobi_mixed_vs_f64": round(r64.seconds / jmx.seconds, 3),
-                    "mg_levels": [lv[0] for lv in op.mg_levels()], "mg_setup_s": round(mg_setup_s, 4),
+                    "mg_levels": mg_lv, "mg_setup_s": round(mg_setup_s, 4),
                     "mg_s": round(rmg.seconds, 4), "mg_iters": rmg.iters, "mg_rel_resid": rmg.rel_resid_true,
                     "mg_rel_diff_x_vs_f64": float((rmg.x - r64.x).norm() / r64.x.norm()),
                     "speedup_mg_vs_f64": round(r64.seconds / rmg.seconds, 3),
-                    "max_err_vs_exact_mg": float((rmg.x - ue).abs().max())})
+                    "max_err_vs_exact_mg": float((rmg.x - ue).abs().max()),
+                    "mg32_setup_s": round(mg32_setup_s, 4), "mg32_s": round(rmg32.seconds, 4),
+                    "mg32_iters": rmg32.iters, "mg32_rel_resid": rmg32.rel_resid_true,
+                    "mg32_rel_diff_x_vs_f64": float((rmg32.x - r64.x).norm() / r64.x.norm()),
+                    "speedup_mg32_vs_f64": round(r64.seconds / rmg32.seconds, 3)})
         print(f"# cg {res[-1]}", file=sys.stderr, flush=True)
         op.close()
         del op

@@ -214,10 +214,14 @@ int mfhex_cg(mfhex_op op, const double *b_dev, double *x_dev, void *cg_work_dev,
  * from 0 (degree), restrict, recurse, prolong and add, post-smooth (degree);
  * the coarsest level is smoothed only (coarse_degree).  Fields left 0 take
  * the defaults degree 3, coarse_degree 8, power_iters 15, all levels,
- * lo 0.25, hi 1.1.  Scalar FP64 diffusion with stored factors and constant
- * kappa only. */
+ * lo 0.25, hi 1.1.  Scalar diffusion with stored factors and constant kappa
+ * only.  precision: MFHEX_F64 (default) or MFHEX_F32, the arithmetic of the
+ * V-cycle (level operators, smoothers, transfers; needs an operator created
+ * with MFHEX_FLAG_F32); set-up (diagonals, power method) is FP64 either way
+ * and mfhex_mg_apply takes and returns FP64 vectors. */
 typedef struct {
     int32_t degree, coarse_degree, power_iters, max_levels;
+    int32_t precision, pad_;
     double lo, hi;
 } mfhex_mg_opts;
 

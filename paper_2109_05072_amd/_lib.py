@@ -63,7 +63,8 @@ class mfhex_cg_opts(C.Structure):
 
 class mfhex_mg_opts(C.Structure):
     _fields_ = [("degree", C.c_int32), ("coarse_degree", C.c_int32), ("power_iters", C.c_int32),
-                ("max_levels", C.c_int32), ("lo", C.c_double), ("hi", C.c_double)]
+                ("max_levels", C.c_int32), ("precision", C.c_int32), ("pad_", C.c_int32), ("lo", C.c_double),
+                ("hi", C.c_double)]
 
 
 class mfhex_cg_stats(C.Structure):

@@ -33,12 +33,12 @@ namespace {
 
 size_t al(size_t b) { return (b + 255) & ~size_t(255); }
 
-mfhex_desc level_desc(const mfhex_desc &fine, int p)
+mfhex_desc level_desc(const mfhex_desc &fine, int p, int prec)
 {
     mfhex_desc d = fine;
     d.p = p;
     d.q = fine.quad == MFHEX_GAUSS ? p + 2 : p + 1;
-    d.flags = 0;
+    d.flags = prec == MFHEX_F32 ? MFHEX_FLAG_F32 : 0u;
     d.variable_kappa = 0;
     d.ncomp = 1;
     return d;
@@ -50,14 +50,15 @@ int64_t n_nodes(const mfhex_desc &d)
 }
 
 struct Opts {
-    int degree, coarse_degree, power_iters, max_levels;
+    int degree, coarse_degree, power_iters, max_levels, prec;
     double lo, hi;
 };
 
 Opts resolve(const mfhex_mg_opts *o)
 {
-    Opts r{3, 8, 15, 0, 0.25, 1.1};
+    Opts r{3, 8, 15, 0, MFHEX_F64, 0.25, 1.1};
     if (o) {
+        r.prec = o->precision;
         if (o->degree > 0) r.degree = o->degree;
         if (o->coarse_degree > 0) r.coarse_degree = o->coarse_degree;
         if (o->power_iters > 0) r.power_iters = o->power_iters;
@@ -68,40 +69,53 @@ Opts resolve(const mfhex_mg_opts *o)
     return r;
 }
 
-// Work-buffer layout: per coarse level an operator workspace, then per level its vectors,
-// then the interpolation matrices and the reduction scratch.
+size_t elem_bytes(int prec) { return prec == MFHEX_F32 ? sizeof(float) : sizeof(double); }
+
+// Work-buffer layout: per coarse level an operator workspace; per level the FP64 inverse
+// diagonal and the cycle vectors (FP64 cycle: r, d, ad, and b, x below the fine level, the
+// inverse diagonal being the FP64 one; FP32 cycle: dinv, r, d, ad, b, x on every level); the
+// interpolation matrices in the cycle precision; the reduction scratch; and for an FP32 cycle
+// two FP64 fine-level vectors for the power method.
 struct MgLayout {
-    std::vector<size_t> ws, ws_bytes, vec, mat;
-    size_t partial = 0, total = 0;
+    std::vector<size_t> ws, ws_bytes, dinv64, vec, mat;
+    size_t partial = 0, power = 0, total = 0;
 };
 
-MgLayout mg_layout(const mfhex_desc &fine, const std::vector<int> &orders)
+MgLayout mg_layout(const mfhex_desc &fine, const std::vector<int> &orders, int prec)
 {
     MgLayout L;
     size_t o = 0;
     const int nl = (int)orders.size();
+    const size_t eb = elem_bytes(prec);
     L.ws.assign(nl, 0);
     L.ws_bytes.assign(nl, 0);
+    L.dinv64.assign(nl, 0);
     L.vec.assign(nl, 0);
     L.mat.assign(nl, 0);
     for (int l = 1; l < nl; ++l) {
-        const mfhex_desc d = level_desc(fine, orders[l]);
+        const mfhex_desc d = level_desc(fine, orders[l], prec);
         const int64_t E = (int64_t)d.nex * d.ney * d.nez;
         L.ws[l] = o;
         L.ws_bytes[l] = workspace_layout(d, E, d.p + 1, d.q).total;
         o += al(L.ws_bytes[l]);
     }
     for (int l = 0; l < nl; ++l) {
-        const int64_t n = n_nodes(level_desc(fine, orders[l]));
+        const int64_t n = n_nodes(level_desc(fine, orders[l], prec));
+        L.dinv64[l] = o;
+        o += al(n * sizeof(double));
         L.vec[l] = o;
-        o += (l == 0 ? 4 : 6) * al(n * sizeof(double));  // dinv, r, d, ad (+ b, x below the fine level)
+        o += (prec == MFHEX_F32 ? 6 : l == 0 ? 3 : 5) * al(n * eb);
     }
     for (int l = 0; l + 1 < nl; ++l) {
         L.mat[l] = o;
-        o += al((size_t)(orders[l] + 1) * (orders[l + 1] + 1) * sizeof(double));
+        o += al((size_t)(orders[l] + 1) * (orders[l + 1] + 1) * eb);
     }
     L.partial = o;
     o += al(2 * kRedBlocks * sizeof(double));
+    if (prec == MFHEX_F32) {
+        L.power = o;
+        o += 2 * al(n_nodes(fine) * sizeof(double));
+    }
     L.total = o;
     return L;
 }
@@ -136,71 +150,76 @@ double read_dot(mfhex_op op, double *partial, hipStream_t s, int *err)
     return h;
 }
 
-// Power method on D^-1 A from the counter-based uniform vector (seed), masked.
-int power_lambda(mfhex_op fine, MgLevel &L, double *partial, int iters, hipStream_t s)
+// Power method on D^-1 A (FP64) from the counter-based uniform vector (seed), masked; v, av:
+// FP64 work vectors of L.n entries.
+int power_lambda(mfhex_op fine, MgLevel &L, double *v, double *av, double *partial, int iters, hipStream_t s)
 {
     const int64_t n = L.n;
     int e = 0;
-    double *v = L.r, *av = L.ad;
     TRY(check_hip(fine, launch_fill_uniform(v, n, 2024, s), "fill"));
-    TRY(check_hip(fine, launch_mask_scale(v, L.dinv, 0.0, n, s), "mask"));
+    TRY(check_hip(fine, launch_mask_scale(v, L.dinv64, 0.0, n, s), "mask"));
     TRY(check_hip(fine, launch_dot(v, MFHEX_F64, v, MFHEX_F64, n, partial, s), "dot"));
     double nv = read_dot(fine, partial, s, &e);
     if (e) return e;
-    TRY(check_hip(fine, launch_mask_scale(v, L.dinv, 1.0 / std::sqrt(nv), n, s), "scale"));
+    TRY(check_hip(fine, launch_mask_scale(v, L.dinv64, 1.0 / std::sqrt(nv), n, s), "scale"));
     double lam = 0.0;
     for (int k = 0; k < iters; ++k) {
         TRY(apply_impl(L.op, MFHEX_F64, 1, v, av, s, true, -1));
         TRY(check_hip(fine, launch_dot(v, MFHEX_F64, av, MFHEX_F64, n, partial, s), "dot"));
         const double vav = read_dot(fine, partial, s, &e);
         if (e) return e;
-        TRY(check_hip(fine, launch_dot_dinv(v, L.dinv, n, partial, s), "dot"));
+        TRY(check_hip(fine, launch_dot_dinv(v, L.dinv64, n, partial, s), "dot"));
         const double vdv = read_dot(fine, partial, s, &e);
         if (e) return e;
         lam = vav / vdv;
-        TRY(check_hip(fine, launch_scale_by(av, L.dinv, v, n, s), "scale"));  // v = dinv A v
+        TRY(check_hip(fine, launch_scale_by(av, L.dinv64, v, n, s), "scale"));  // v = dinv A v
         TRY(check_hip(fine, launch_dot(v, MFHEX_F64, v, MFHEX_F64, n, partial, s), "dot"));
         nv = read_dot(fine, partial, s, &e);
         if (e) return e;
-        TRY(check_hip(fine, launch_mask_scale(v, L.dinv, 1.0 / std::sqrt(nv), n, s), "scale"));
+        TRY(check_hip(fine, launch_mask_scale(v, L.dinv64, 1.0 / std::sqrt(nv), n, s), "scale"));
     }
     if (!(lam > 0.0) || !std::isfinite(lam)) return set_error(fine, MFHEX_ERR_BREAKDOWN, "power method failed");
     L.lam = lam;
     return MFHEX_OK;
 }
 
-// Degree-k Chebyshev smoother on level L: x <- S(b, x) (x = 0 when zero_x).
-int chebyshev(mfhex_op fine, const MgHierarchy &h, const MgLevel &L, const double *b, double *x, int degree,
+// Degree-k Chebyshev smoother on level L: x <- S(b, x) (x = 0 when zero_x), vectors in the
+// cycle precision; the recurrence coefficients are formed in FP64 on the host.
+int chebyshev(mfhex_op fine, const MgHierarchy &h, const MgLevel &L, const void *b, void *x, int degree,
               bool zero_x, hipStream_t s)
 {
     const double lo = h.lo * L.lam, hi = h.hi * L.lam;
     const double theta = 0.5 * (hi + lo), delta = 0.5 * (hi - lo), sigma = theta / delta;
-    if (!zero_x) TRY(apply_impl(L.op, MFHEX_F64, 1, x, L.ad, s, true, -1));
-    TRY(check_hip(fine, launch_cheb_init(b, zero_x ? nullptr : L.ad, L.dinv, x, L.r, L.d, 1.0 / theta, zero_x, L.n, s),
+    if (!zero_x) TRY(apply_impl(L.op, h.prec, 1, x, L.ad, s, true, -1));
+    TRY(check_hip(fine,
+                  launch_cheb_init(b, zero_x ? nullptr : L.ad, L.dinv, x, L.r, L.d, 1.0 / theta, zero_x, h.prec,
+                                   L.n, s),
                   "chebyshev kernel"));
     double rho = 1.0 / sigma;
     for (int k = 0; k < degree; ++k) {
         const bool last = k == degree - 1;
         double cd = 0.0, cr = 0.0;
         if (!last) {
-            TRY(apply_impl(L.op, MFHEX_F64, 1, L.d, L.ad, s, true, -1));
+            TRY(apply_impl(L.op, h.prec, 1, L.d, L.ad, s, true, -1));
             const double rho_new = 1.0 / (2.0 * sigma - rho);
             cd = rho_new * rho;
             cr = 2.0 * rho_new / delta;
             rho = rho_new;
         }
-        TRY(check_hip(fine, launch_cheb_step(x, L.d, L.r, L.ad, L.dinv, cd, cr, last, L.n, s), "chebyshev kernel"));
+        TRY(check_hip(fine, launch_cheb_step(x, L.d, L.r, L.ad, L.dinv, cd, cr, last, h.prec, L.n, s),
+                      "chebyshev kernel"));
     }
     return MFHEX_OK;
 }
 
-int transfer(mfhex_op fine, const MgLevel &F, const MgLevel &Cl, int dir, const double *src, double *dst,
-             hipStream_t s)
+int transfer(mfhex_op fine, const MgHierarchy &h, const MgLevel &F, const MgLevel &Cl, int dir, const void *src,
+             void *dst, hipStream_t s)
 {
     TransferLaunch t{};
     t.pf = F.p;
     t.pc = Cl.p;
     t.dir = dir;
+    t.prec = h.prec;
     t.nex = fine->d.nex;
     t.ney = fine->d.ney;
     t.nez = fine->d.nez;
@@ -213,18 +232,18 @@ int transfer(mfhex_op fine, const MgLevel &F, const MgLevel &Cl, int dir, const 
     return check_hip(fine, launch_transfer(t), "transfer kernel");
 }
 
-int vcycle(mfhex_op fine, MgHierarchy &h, int l, const double *b, double *x, hipStream_t s)
+int vcycle(mfhex_op fine, MgHierarchy &h, int l, const void *b, void *x, hipStream_t s)
 {
     MgLevel &L = h.lv[l];
     if (l + 1 == (int)h.lv.size()) return chebyshev(fine, h, L, b, x, h.coarse_degree, true, s);
     TRY(chebyshev(fine, h, L, b, x, h.degree, true, s));
-    TRY(apply_impl(L.op, MFHEX_F64, 1, x, L.ad, s, true, -1));
-    TRY(check_hip(fine, launch_residual(b, L.ad, L.r, nullptr, L.n, h.partial, s), "residual kernel"));
+    TRY(apply_impl(L.op, h.prec, 1, x, L.ad, s, true, -1));
+    TRY(check_hip(fine, launch_mg_residual(b, L.ad, L.r, h.prec, L.n, s), "residual kernel"));
     MgLevel &Cl = h.lv[l + 1];
-    TRY(check_hip(fine, hipMemsetAsync(Cl.b, 0, Cl.n * sizeof(double), s), "hipMemsetAsync"));
-    TRY(transfer(fine, L, Cl, 1, L.r, Cl.b, s));
+    TRY(check_hip(fine, hipMemsetAsync(Cl.b, 0, Cl.n * elem_bytes(h.prec), s), "hipMemsetAsync"));
+    TRY(transfer(fine, h, L, Cl, 1, L.r, Cl.b, s));
     TRY(vcycle(fine, h, l + 1, Cl.b, Cl.x, s));
-    TRY(transfer(fine, L, Cl, 0, Cl.x, x, s));
+    TRY(transfer(fine, h, L, Cl, 0, Cl.x, x, s));
     return chebyshev(fine, h, L, b, x, h.degree, false, s);
 }
 
@@ -235,7 +254,12 @@ int mg_vcycle(mfhex_op op, const double *r, double *z, hipStream_t s)
     if (!op) return set_error(nullptr, MFHEX_ERR_ARG, "null handle");
     if (!op->mg) return set_error(op, MFHEX_ERR_STATE, "no multigrid hierarchy (mfhex_mg_setup)");
     if (!r || !z) return set_error(op, MFHEX_ERR_ARG, "null vector");
-    return vcycle(op, *op->mg, 0, r, z, s);
+    MgHierarchy &h = *op->mg;
+    if (h.prec != MFHEX_F32) return vcycle(op, h, 0, r, z, s);
+    MgLevel &L0 = h.lv[0];
+    TRY(check_hip(op, launch_copy(r, MFHEX_F64, L0.b, MFHEX_F32, L0.n, s), "copy kernel"));
+    TRY(vcycle(op, h, 0, L0.b, L0.x, s));
+    return check_hip(op, launch_copy(L0.x, MFHEX_F32, z, MFHEX_F64, L0.n, s), "copy kernel");
 }
 
 void mg_release(mfhex_op op)
@@ -261,8 +285,11 @@ int mfhex_mg_query(const mfhex_desc *fine, const mfhex_mg_opts *opts, size_t *wo
                            "multigrid: scalar diffusion with stored geometric factors and constant kappa only");
     }
     const Opts o = resolve(opts);
+    if (o.prec != MFHEX_F64 && o.prec != MFHEX_F32) return fail_global(MFHEX_ERR_ARG, "multigrid: bad precision");
+    if (o.prec == MFHEX_F32 && !(fine->flags & MFHEX_FLAG_F32))
+        return fail_global(MFHEX_ERR_ARG, "multigrid: an FP32 cycle needs an operator created with MFHEX_FLAG_F32");
     const std::vector<int> orders = mg_orders(fine->p, o.max_levels);
-    if (work_bytes) *work_bytes = mg_layout(*fine, orders).total;
+    if (work_bytes) *work_bytes = mg_layout(*fine, orders, o.prec).total;
     if (nlevels) *nlevels = (int32_t)orders.size();
     return MFHEX_OK;
 }
@@ -277,7 +304,7 @@ int mfhex_mg_setup(mfhex_op op, const mfhex_desc *fine, const mfhex_mg_opts *opt
     if (c) return set_error(op, c, mfhex_last_error(nullptr));
     if (fine->p != op->d.p || fine->q != op->d.q || fine->nex != op->d.nex || fine->ney != op->d.ney ||
         fine->nez != op->d.nez || fine->quad != op->d.quad || fine->dirichlet != op->d.dirichlet ||
-        fine->kind != op->d.kind)
+        fine->kind != op->d.kind || fine->flags != op->d.flags)
         return set_error(op, MFHEX_ERR_ARG, "description does not match the operator");
     if (!work_dev || ((uintptr_t)work_dev & 255) || work_bytes < need)
         return set_error(op, MFHEX_ERR_ARG, "multigrid work area missing, misaligned or too small (mfhex_mg_query)");
@@ -285,9 +312,11 @@ int mfhex_mg_setup(mfhex_op op, const mfhex_desc *fine, const mfhex_mg_opts *opt
     mg_release(op);
     const Opts o = resolve(opts);
     const std::vector<int> orders = mg_orders(fine->p, o.max_levels);
-    const MgLayout L = mg_layout(*fine, orders);
+    const MgLayout L = mg_layout(*fine, orders, o.prec);
+    const size_t eb = elem_bytes(o.prec);
     char *w = static_cast<char *>(work_dev);
     auto h = std::make_unique<MgHierarchy>();
+    h->prec = o.prec;
     h->degree = o.degree;
     h->coarse_degree = o.coarse_degree;
     h->power_iters = o.power_iters;
@@ -301,7 +330,7 @@ int mfhex_mg_setup(mfhex_op op, const mfhex_desc *fine, const mfhex_mg_opts *opt
     };
     for (size_t l = 0; l < orders.size(); ++l) {
         MgLevel &lv = h->lv[l];
-        const mfhex_desc d = level_desc(*fine, orders[l]);
+        const mfhex_desc d = level_desc(*fine, orders[l], o.prec);
         lv.p = orders[l];
         lv.n = n_nodes(d);
         if (l == 0) {
@@ -310,20 +339,28 @@ int mfhex_mg_setup(mfhex_op op, const mfhex_desc *fine, const mfhex_mg_opts *opt
             lv.op = nullptr;
             return cleanup(set_error(op, c, std::string("coarse level: ") + mfhex_last_error(nullptr)));
         }
-        const size_t vb = al(lv.n * sizeof(double));
-        double *v = reinterpret_cast<double *>(w + L.vec[l]);
-        lv.dinv = v;
-        lv.r = reinterpret_cast<double *>(reinterpret_cast<char *>(v) + vb);
-        lv.d = reinterpret_cast<double *>(reinterpret_cast<char *>(v) + 2 * vb);
-        lv.ad = reinterpret_cast<double *>(reinterpret_cast<char *>(v) + 3 * vb);
-        if (l > 0) {
-            lv.b = reinterpret_cast<double *>(reinterpret_cast<char *>(v) + 4 * vb);
-            lv.x = reinterpret_cast<double *>(reinterpret_cast<char *>(v) + 5 * vb);
+        const size_t vb = al(lv.n * eb);
+        char *v = w + L.vec[l];
+        lv.dinv64 = reinterpret_cast<double *>(w + L.dinv64[l]);
+        int k = 0;
+        lv.dinv = o.prec == MFHEX_F32 ? static_cast<void *>(v + vb * k++) : lv.dinv64;
+        lv.r = v + vb * k++;
+        lv.d = v + vb * k++;
+        lv.ad = v + vb * k++;
+        if (l > 0 || o.prec == MFHEX_F32) {
+            lv.b = v + vb * k++;
+            lv.x = v + vb * k++;
         }
-        if ((c = diagonal_impl(lv.op, lv.dinv, s))) return cleanup(set_error(op, c, lv.op->err));
-        if ((c = check_hip(op, launch_jacobi_inverse(lv.dinv, lv.dinv, nullptr, lv.n, s), "inverse kernel")))
+        if ((c = diagonal_impl(lv.op, lv.dinv64, s))) return cleanup(set_error(op, c, lv.op->err));
+        float *dinv32 = o.prec == MFHEX_F32 ? static_cast<float *>(lv.dinv) : nullptr;
+        if ((c = check_hip(op, launch_jacobi_inverse(lv.dinv64, lv.dinv64, dinv32, lv.n, s), "inverse kernel")))
             return cleanup(c);
-        if ((c = power_lambda(op, lv, h->partial, h->power_iters, s))) return cleanup(c);
+        double *pv = static_cast<double *>(lv.r), *pav = static_cast<double *>(lv.ad);
+        if (o.prec == MFHEX_F32) {
+            pv = reinterpret_cast<double *>(w + L.power);
+            pav = reinterpret_cast<double *>(w + L.power + al(n_nodes(*fine) * sizeof(double)));
+        }
+        if ((c = power_lambda(op, lv, pv, pav, h->partial, h->power_iters, s))) return cleanup(c);
     }
     for (size_t l = 0; l + 1 < orders.size(); ++l) {
         Basis1D bf, bc;
@@ -331,8 +368,10 @@ int mfhex_mg_setup(mfhex_op op, const mfhex_desc *fine, const mfhex_mg_opts *opt
         build_basis(orders[l], orders[l] + 1, MFHEX_GLL, &bf, &e);
         build_basis(orders[l + 1], orders[l + 1] + 1, MFHEX_GLL, &bc, &e);
         const std::vector<double> M = interp_matrix(bc.nodes, orders[l + 1] + 1, bf.nodes, orders[l] + 1);
-        h->lv[l].I1 = reinterpret_cast<double *>(w + L.mat[l]);
-        if ((c = check_hip(op, hipMemcpy(h->lv[l].I1, M.data(), M.size() * sizeof(double), hipMemcpyHostToDevice),
+        const std::vector<float> M32(M.begin(), M.end());
+        h->lv[l].I1 = w + L.mat[l];
+        const void *src = o.prec == MFHEX_F32 ? static_cast<const void *>(M32.data()) : M.data();
+        if ((c = check_hip(op, hipMemcpy(h->lv[l].I1, src, M.size() * eb, hipMemcpyHostToDevice),
                            "copy interpolation")))
             return cleanup(c);
     }

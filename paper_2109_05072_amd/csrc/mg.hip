@@ -29,10 +29,10 @@ __device__ __forceinline__ double share_weight(int i, int j, int k, int P, int e
     return 1.0 / (mx * my * mz);
 }
 
-template <int PF, int PC, int DIR>
+template <int PF, int PC, int DIR, typename T>
 __global__ void __launch_bounds__(kTransferThreads)
 k_transfer(int nex, int ney, int nez, const int32_t *__restrict__ off_f, const int32_t *__restrict__ off_c,
-           const double *__restrict__ I1, const double *__restrict__ src, double *__restrict__ dst)
+           const T *__restrict__ I1, const T *__restrict__ src, T *__restrict__ dst)
 {
     constexpr int NT = kTransferThreads;
     constexpr int F3 = PF * PF * PF, C3 = PC * PC * PC;
@@ -41,7 +41,7 @@ k_transfer(int nex, int ney, int nez, const int32_t *__restrict__ off_f, const i
     constexpr int NA = DIR == 0 ? C3 : F3;
     constexpr int NB = DIR == 0 ? PC * PC * PF : PF * PF * PC;
     constexpr int NC = DIR == 0 ? PC * PF * PF : PF * PC * PC;
-    __shared__ double sI[PF * PC], sa[NA], sb[NB], sc[NC];
+    __shared__ T sI[PF * PC], sa[NA], sb[NB], sc[NC];
     const int tid = threadIdx.x;
     const int64_t e = blockIdx.x;
     const int ex = (int)(e % nex), ey = (int)((e / nex) % ney), ez = (int)(e / ((int64_t)nex * ney));
@@ -49,13 +49,13 @@ k_transfer(int nex, int ney, int nez, const int32_t *__restrict__ off_f, const i
     if constexpr (DIR == 0) {
         for (int t = tid; t < C3; t += NT) {
             const int32_t o = off_c[e * C3 + t];
-            sa[t] = o >= 0 ? src[o] : 0.0;
+            sa[t] = o >= 0 ? src[o] : T(0);
         }
     } else {
         for (int t = tid; t < F3; t += NT) {
             const int32_t o = off_f[e * F3 + t];
             const int i = t % PF, j = (t / PF) % PF, k = t / (PF * PF);
-            sa[t] = o >= 0 ? share_weight(i, j, k, PF, ex, ey, ez, nex, ney, nez) * src[o] : 0.0;
+            sa[t] = o >= 0 ? T(share_weight(i, j, k, PF, ex, ey, ez, nex, ney, nez)) * src[o] : T(0);
         }
     }
     __syncthreads();
@@ -63,7 +63,7 @@ k_transfer(int nex, int ney, int nez, const int32_t *__restrict__ off_f, const i
     constexpr int NIX = DIR == 0 ? PC : PF, NOX = DIR == 0 ? PF : PC;
     for (int t = tid; t < NB; t += NT) {
         const int o = t % NOX, rest = t / NOX;
-        double s = 0.0;
+        T s = T(0);
         for (int i = 0; i < NIX; ++i)
             s += (DIR == 0 ? sI[o * PC + i] : sI[i * PC + o]) * sa[i + NIX * rest];
         sb[t] = s;
@@ -74,7 +74,7 @@ k_transfer(int nex, int ney, int nez, const int32_t *__restrict__ off_f, const i
     constexpr int NIY = DIR == 0 ? PC : PF, NOY = DIR == 0 ? PF : PC;
     for (int t = tid; t < NC; t += NT) {
         const int a = t % NX, o = (t / NX) % NOY, z = t / (NX * NOY);
-        double s = 0.0;
+        T s = T(0);
         for (int j = 0; j < NIY; ++j)
             s += (DIR == 0 ? sI[o * PC + j] : sI[j * PC + o]) * sb[a + NX * (j + NIY * z)];
         sc[t] = s;
@@ -84,13 +84,13 @@ k_transfer(int nex, int ney, int nez, const int32_t *__restrict__ off_f, const i
     constexpr int NIZ = DIR == 0 ? PC : PF, NOZ = DIR == 0 ? PF : PC, NXY = NX * NOY;
     for (int t = tid; t < NOZ * NXY; t += NT) {
         const int ab = t % NXY, o = t / NXY;
-        double s = 0.0;
+        T s = T(0);
         for (int k = 0; k < NIZ; ++k) s += (DIR == 0 ? sI[o * PC + k] : sI[k * PC + o]) * sc[ab + NXY * k];
         if constexpr (DIR == 0) {
             const int32_t of = off_f[e * F3 + t];
             if (of >= 0) {
                 const int i = t % PF, j = (t / PF) % PF, k = t / (PF * PF);
-                unsafeAtomicAdd(&dst[of], share_weight(i, j, k, PF, ex, ey, ez, nex, ney, nez) * s);
+                unsafeAtomicAdd(&dst[of], T(share_weight(i, j, k, PF, ex, ey, ez, nex, ney, nez)) * s);
             }
         } else {
             const int32_t oc = off_c[e * C3 + t];
@@ -99,46 +99,61 @@ k_transfer(int nex, int ney, int nez, const int32_t *__restrict__ off_f, const i
     }
 }
 
+template <int PF, int PC, typename T>
+hipError_t transfer_t(const TransferLaunch &t)
+{
+    const int64_t nelem = (int64_t)t.nex * t.ney * t.nez;
+    const T *I1 = static_cast<const T *>(t.I1), *src = static_cast<const T *>(t.src);
+    T *dst = static_cast<T *>(t.dst);
+    if (t.dir == 0)
+        hipLaunchKernelGGL((k_transfer<PF, PC, 0, T>), dim3((unsigned)nelem), dim3(kTransferThreads), 0, t.stream,
+                           t.nex, t.ney, t.nez, t.off_f, t.off_c, I1, src, dst);
+    else
+        hipLaunchKernelGGL((k_transfer<PF, PC, 1, T>), dim3((unsigned)nelem), dim3(kTransferThreads), 0, t.stream,
+                           t.nex, t.ney, t.nez, t.off_f, t.off_c, I1, src, dst);
+    return hipGetLastError();
+}
+
 template <int PF, int PC>
 hipError_t transfer_pf(const TransferLaunch &t)
 {
-    const int64_t nelem = (int64_t)t.nex * t.ney * t.nez;
-    if (t.dir == 0)
-        hipLaunchKernelGGL((k_transfer<PF, PC, 0>), dim3((unsigned)nelem), dim3(kTransferThreads), 0, t.stream, t.nex,
-                           t.ney, t.nez, t.off_f, t.off_c, t.I1, t.src, t.dst);
-    else
-        hipLaunchKernelGGL((k_transfer<PF, PC, 1>), dim3((unsigned)nelem), dim3(kTransferThreads), 0, t.stream, t.nex,
-                           t.ney, t.nez, t.off_f, t.off_c, t.I1, t.src, t.dst);
-    return hipGetLastError();
+    return t.prec == MFHEX_F32 ? transfer_t<PF, PC, float>(t) : transfer_t<PF, PC, double>(t);
 }
 
 #define GRID dim3(kRedBlocks), dim3(kRedThreads), 0, s
 
-__global__ void k_cheb_init(const double *__restrict__ b, const double *__restrict__ Ax, const double *__restrict__ dinv,
-                            double *__restrict__ x, double *__restrict__ r, double *__restrict__ d, double inv_theta,
-                            int zero_x, int64_t n)
+template <typename T>
+__global__ void k_cheb_init(const T *__restrict__ b, const T *__restrict__ Ax, const T *__restrict__ dinv,
+                            T *__restrict__ x, T *__restrict__ r, T *__restrict__ d, T inv_theta, int zero_x, int64_t n)
 {
     for (int64_t i = blockIdx.x * (int64_t)kRedThreads + threadIdx.x; i < n; i += (int64_t)kRedBlocks * kRedThreads) {
-        const double ri = dinv[i] * (Ax ? b[i] - Ax[i] : b[i]);
+        const T ri = dinv[i] * (Ax ? b[i] - Ax[i] : b[i]);
         r[i] = ri;
         d[i] = ri * inv_theta;
-        if (zero_x) x[i] = 0.0;
+        if (zero_x) x[i] = T(0);
     }
 }
 
-__global__ void k_cheb_step(double *__restrict__ x, double *__restrict__ d, double *__restrict__ r,
-                            const double *__restrict__ Ad, const double *__restrict__ dinv, double cd, double cr,
-                            int last, int64_t n)
+template <typename T>
+__global__ void k_cheb_step(T *__restrict__ x, T *__restrict__ d, T *__restrict__ r, const T *__restrict__ Ad,
+                            const T *__restrict__ dinv, T cd, T cr, int last, int64_t n)
 {
     for (int64_t i = blockIdx.x * (int64_t)kRedThreads + threadIdx.x; i < n; i += (int64_t)kRedBlocks * kRedThreads) {
-        const double di = d[i];
+        const T di = d[i];
         x[i] += di;
         if (!last) {
-            const double ri = r[i] - dinv[i] * Ad[i];
+            const T ri = r[i] - dinv[i] * Ad[i];
             r[i] = ri;
             d[i] = cd * di + cr * ri;
         }
     }
+}
+
+template <typename T>
+__global__ void k_mg_residual(const T *__restrict__ b, const T *__restrict__ Ax, T *__restrict__ r, int64_t n)
+{
+    for (int64_t i = blockIdx.x * (int64_t)kRedThreads + threadIdx.x; i < n; i += (int64_t)kRedBlocks * kRedThreads)
+        r[i] = b[i] - Ax[i];
 }
 
 __global__ void k_mask_scale(double *__restrict__ v, const double *__restrict__ dinv, double scale, int64_t n)
@@ -188,17 +203,36 @@ hipError_t launch_transfer(const TransferLaunch &t)
     }
 }
 
-hipError_t launch_cheb_init(const double *b, const double *Ax, const double *dinv, double *x, double *r, double *d,
-                            double inv_theta, bool zero_x, int64_t n, hipStream_t s)
+hipError_t launch_cheb_init(const void *b, const void *Ax, const void *dinv, void *x, void *r, void *d,
+                            double inv_theta, bool zero_x, int prec, int64_t n, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_cheb_init, GRID, b, Ax, dinv, x, r, d, inv_theta, zero_x ? 1 : 0, n);
+    if (prec == MFHEX_F32)
+        hipLaunchKernelGGL(k_cheb_init<float>, GRID, (const float *)b, (const float *)Ax, (const float *)dinv,
+                           (float *)x, (float *)r, (float *)d, (float)inv_theta, zero_x ? 1 : 0, n);
+    else
+        hipLaunchKernelGGL(k_cheb_init<double>, GRID, (const double *)b, (const double *)Ax, (const double *)dinv,
+                           (double *)x, (double *)r, (double *)d, inv_theta, zero_x ? 1 : 0, n);
     return hipGetLastError();
 }
 
-hipError_t launch_cheb_step(double *x, double *d, double *r, const double *Ad, const double *dinv, double cd, double cr,
-                            bool last, int64_t n, hipStream_t s)
+hipError_t launch_cheb_step(void *x, void *d, void *r, const void *Ad, const void *dinv, double cd, double cr,
+                            bool last, int prec, int64_t n, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_cheb_step, GRID, x, d, r, Ad, dinv, cd, cr, last ? 1 : 0, n);
+    if (prec == MFHEX_F32)
+        hipLaunchKernelGGL(k_cheb_step<float>, GRID, (float *)x, (float *)d, (float *)r, (const float *)Ad,
+                           (const float *)dinv, (float)cd, (float)cr, last ? 1 : 0, n);
+    else
+        hipLaunchKernelGGL(k_cheb_step<double>, GRID, (double *)x, (double *)d, (double *)r, (const double *)Ad,
+                           (const double *)dinv, cd, cr, last ? 1 : 0, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_mg_residual(const void *b, const void *Ax, void *r, int prec, int64_t n, hipStream_t s)
+{
+    if (prec == MFHEX_F32)
+        hipLaunchKernelGGL(k_mg_residual<float>, GRID, (const float *)b, (const float *)Ax, (float *)r, n);
+    else
+        hipLaunchKernelGGL(k_mg_residual<double>, GRID, (const double *)b, (const double *)Ax, (double *)r, n);
     return hipGetLastError();
 }
 

@@ -193,9 +193,10 @@ class Operator:
 
     # -- p-multigrid -------------------------------------------------------------------------
     def mg_setup(self, degree: int = 0, coarse_degree: int = 0, power_iters: int = 0, max_levels: int = 0,
-                 lo: float = 0.0, hi: float = 0.0) -> int:
-        """Build the p-multigrid hierarchy (levels p, p/2, ..., 1); 0 keeps a default.  Returns the level count."""
-        opts = L.mfhex_mg_opts(degree, coarse_degree, power_iters, max_levels, lo, hi)
+                 lo: float = 0.0, hi: float = 0.0, dtype: torch.dtype = torch.float64) -> int:
+        """Build the p-multigrid hierarchy (levels p, p/2, ..., 1); 0 keeps a default.  dtype: arithmetic of
+        the V-cycle (float32 needs an operator built with f32=True).  Returns the level count."""
+        opts = L.mfhex_mg_opts(degree, coarse_degree, power_iters, max_levels, _prec(dtype), 0, lo, hi)
         nbytes, nl = L.mfhex_mg_query(self.desc, opts)
         self._mg_work = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
         ptr = (self._mg_work.data_ptr() + 255) & ~255

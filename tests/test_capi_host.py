@@ -130,3 +130,11 @@ def test_cg_option_struct_layout():
     assert L.mfhex_cg_opts.rtol.offset == 32 and L.mfhex_cg_opts.precond.offset == 24
     src = open(os.path.join(ROOT, "include", "mfhex.h")).read()
     assert "max_iters_exact, precond, pad_;" in src
+
+
+def test_mg_option_struct_layout():
+    # int32 degree, coarse_degree, power_iters, max_levels, precision, pad_; double lo, hi
+    assert C.sizeof(L.mfhex_mg_opts) == 40
+    assert L.mfhex_mg_opts.precision.offset == 16 and L.mfhex_mg_opts.lo.offset == 24
+    src = open(os.path.join(ROOT, "include", "mfhex.h")).read()
+    assert "int32_t precision, pad_;" in src

@@ -545,6 +545,45 @@ def test_mg_pcg_matches_oracle(gpu_lib, p, ne):
     assert relerr(host(res.x), xo) <= 1e-7
 
 
+@pytest.mark.parametrize("p,quad", [(2, "gauss"), (3, "gauss"), (5, "gauss"), (8, "gauss"), (6, "gll")])
+def test_mg_fp32_vcycle_matches_oracle(gpu_lib, p, quad):
+    # FP32 V-cycle against the FP64 oracle cycle: set-up (diagonals, power method) is FP64 in both,
+    # so the level eigenvalue estimates agree to FP64 rounding; the cycle is a chain of some forty
+    # FP32 operator applies and vector updates, each adding about one unit roundoff (2^-24) of
+    # relative error to a result of the same scale, so the cycle is held to 40 x 2^-24.
+    from oracle import multigrid as omg
+    _say("mg vcycle fp32", p, quad)
+    op, pr = build(gpu_lib, 3, 2, 2, p, "diffusion", quad, True, f32=True)
+    op.mg_setup(dtype=torch.float32)
+    h = omg.Hierarchy(pr)
+    for (pl, nl_nodes, lam), L in zip(op.mg_levels(), h.levels):
+        assert pl == L["pr"].p and abs(lam - L["lam"]) <= 1e-10 * L["lam"]
+    r = synth.uniform_vector(pr.n_nodes, seed=5) * interior_mask(pr)
+    z = host(op.mg_apply(dev(r)))
+    zo = h.vcycle(r)
+    print("fp32 vcycle rel diff", relerr(z, zo))
+    assert relerr(z, zo) <= 40 * 2.0 ** -24
+    assert np.all(z[interior_mask(pr) == 0] == 0.0)
+
+
+@pytest.mark.parametrize("p,ne", [(3, 8), (6, 4)])
+def test_mg_fp32_pcg_converges_like_fp64(gpu_lib, p, ne):
+    # FP64 CG with the FP32 V-cycle as preconditioner reaches the same FP64 residual; the
+    # preconditioner is the FP64 one perturbed at FP32 rounding, so the iteration count stays
+    # within a few of the oracle's FP64-preconditioned count.
+    from oracle import multigrid as omg
+    op, pr = build(gpu_lib, ne, ne, ne, p, "diffusion", "gauss", True, f32=True, rhs=True)
+    op.mg_setup(dtype=torch.float32)
+    b = _masked_rhs(op, pr)
+    res = op.cg(b, maxit=500, rtol=1e-10, precond="mg")
+    bo = oracle.rhs(pr, synth.sin_forcing(oracle.qpoint_geometry(pr)[0]))
+    xo, ho, it_o = omg.mg_pcg(omg.Hierarchy(pr), bo, maxit=500, rtol=1e-10)
+    print("mg32 pcg", p, ne, "iters", res.iters, "oracle", it_o)
+    assert res.status == 0 and res.rel_resid_true <= 1e-10
+    assert res.iters <= it_o + 3
+    assert relerr(host(res.x), xo) <= 1e-7
+
+
 def test_mg_rejects_what_it_does_not_support(gpu_lib):
     from paper_2109_05072_amd import _lib as L
     op, pr = build(gpu_lib, 2, 2, 2, 2)
@@ -557,6 +596,9 @@ def test_mg_rejects_what_it_does_not_support(gpu_lib):
         with pytest.raises(L.MFHexError) as ei:
             o2.mg_setup()
         assert ei.value.code == L.MFHEX_ERR_UNSUPPORTED
+    with pytest.raises(L.MFHexError) as ei:
+        op.mg_setup(dtype=torch.float32)  # FP32 cycle on an operator without FP32 data
+    assert ei.value.code == L.MFHEX_ERR_ARG
     o3, _ = build(gpu_lib, 2, 2, 2, 3, f32=True)
     o3.mg_setup()
     with pytest.raises(L.MFHexError) as ei:
