@@ -174,6 +174,11 @@ def main():
                       "launch": {"variant": m["epb"][0], "elements_per_group": m["epb"][1],
                                  "threads_per_group": m["epb"][2], "groups_per_block": m["epb"][3]},
                       "paper_v100_cuda_gen_gdofs": PAPER_V100_CUDA_GEN.get(p)})
+    # measured device-copy rate on this GPU (1 GiB read + 1 GiB written per copy, median of 5): the
+    # practical HBM ceiling next to the datasheet peak
+    copy_gbs = measure_copy_gbs()
+    for r in per_p:
+        r["copy_frac"] = round(r["alg_gbs"] / copy_gbs, 4)
     dom = max(per_p, key=lambda r: r["ms"])
     from paper_2109_05072_amd.prof_summary import read_traffic
     lg = dom["launch"]
@@ -201,7 +206,8 @@ def main():
         "roofline": ({"bound": "hbm", "kernel": dom_name,
                       "achieved": dom["alg_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                       "frac": dom["hbm_frac"], "traffic": traffic.get(dom_name),
-                      "alg_bytes_per_launch": dom["alg_bytes"]}
+                      "alg_bytes_per_launch": dom["alg_bytes"], "measured_copy_gbs": round(copy_gbs, 1),
+                      "frac_of_copy": dom["copy_frac"]}
                      if not args.otf or dom["hbm_frac"] >= dom["fp64_alu_frac"] else
                      {"bound": "alu", "kernel": dom_name, "achieved": dom["alg_tflops"],
                       "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": dom["fp64_alu_frac"],
@@ -229,6 +235,25 @@ def main():
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(dom["p"])
     print(json.dumps(out), flush=True)
+
+
+def measure_copy_gbs(nbytes: int = 1 << 30, reps: int = 5) -> float:
+    """GB/s of a device-to-device copy of nbytes (read + write counted), median of reps."""
+    import torch
+    a = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    ts = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1) / 1e3)
+    del a, b
+    torch.cuda.empty_cache()
+    return 2 * nbytes / float(np.median(ts)) / 1e9
 
 
 def sweep_variants(op, x, p, reps=10, rounds=3, nrhs=1):

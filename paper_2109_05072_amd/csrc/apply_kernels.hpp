@@ -83,8 +83,11 @@ __device__ __forceinline__ void group_sync()
 //   E_o = sum_i Me[o][i] e_i (+ M[o][mid] v_mid),  O_o = sum_i Mo[o][i] d_i,
 //   out_o = E_o + O_o,   out_{NO-1-o} = SYM (E_o - O_o),   o < ceil(NO/2),
 // which halves the multiply-adds; MF points at the folded rows
-// [Me[o][0..NI/2) | Mo[o][0..NI/2) | M[o][mid]].
-template <int AX, int E0, int E1, int E2, int NO, int G, int NT, int Q, int SYM, typename T, bool ADD2 = false>
+// [Me[o][0..NI/2) | Mo[o][0..NI/2) | M[o][mid]].  Only the output pairs
+// OB <= o < OE (default: all) are formed, so that two halves of a group can
+// share one contraction.
+template <int AX, int E0, int E1, int E2, int NO, int G, int NT, int Q, int SYM, typename T, bool ADD2 = false,
+          int OB = 0, int OE = -1>
 __device__ __forceinline__ void contract(const T *src, T *dst, const T *__restrict__ MF, int tid, const T *a1 = nullptr,
                                          const T *a2 = nullptr)
 {
@@ -118,10 +121,11 @@ __device__ __forceinline__ void contract(const T *src, T *dst, const T *__restri
             if constexpr (MID) ev[r][H] = v[H];
         }
     }
+    constexpr int OEND = OE < 0 ? NOH : OE;
     // coefficient half-rows in flight per scalar-load wait: about 24 coefficients
     constexpr int UR = NI >= 12 ? 2 : 24 / NI;
 #pragma unroll UR
-    for (int o = 0; o < NOH; ++o) {
+    for (int o = OB; o < OEND; ++o) {
         const T *row = MF + o * NI;
         const int om = NO - 1 - o;
 #pragma unroll
@@ -329,6 +333,20 @@ __device__ __forceinline__ void grad(T *s0, T *s1, T *s2, const T *__restrict__ 
     group_sync<NT>();
 }
 
+// One contraction shared by the two halves of a split group (one element,
+// NT2 threads per half, every line owned by one lane of each half): half 0
+// forms output pairs o < OM, half 1 the rest.
+template <int AX, int E0, int E1, int E2, int NO, int NT2, int Q, int SYM, typename T, bool ADD2 = false,
+          int OM = ((NO + 1) / 2 + 1) / 2>
+__device__ __forceinline__ void contract_halves(const T *src, T *dst, const T *__restrict__ MF, int half, int lane,
+                                                const T *a1 = nullptr, const T *a2 = nullptr)
+{
+    constexpr int NOH = (NO + 1) / 2;
+    static_assert(E0 * E1 * E2 / (AX == 0 ? E0 : AX == 1 ? E1 : E2) <= NT2, "one line per lane");
+    if (half == 0) contract<AX, E0, E1, E2, NO, 1, NT2, Q, SYM, T, ADD2, 0, OM>(src, dst, MF, lane, a1, a2);
+    else contract<AX, E0, E1, E2, NO, 1, NT2, Q, SYM, T, ADD2, OM, NOH>(src, dst, MF, lane, a1, a2);
+}
+
 // ---------------------------------------------------------------------------
 // y += A x  (diffusion), or y += B^T (w detJ f) for the load vector.
 // VC vectors of the multi-vector travel together (virtual elements g*VC + vc).
@@ -350,6 +368,8 @@ k_apply(const T *__restrict__ bas, const int nex, const int ney, const int nvec,
     constexpr int Q2 = Q * Q, Q3 = Q2 * Q;
     constexpr int NPT = G * Q3, RQ = (NPT + NT - 1) / NT;
     constexpr int GV = G * VC;
+    constexpr bool SPLIT = split_stages(Q, MODE, G, NT, VC);
+    constexpr int NT2 = NT / 2;
     static_assert(MODE != kMass, "the mass operator runs in k_mass");
     static_assert(!OTF || (MODE == kDiff && !VARK && VC == 1 && sizeof(T) == 8), "in-kernel factors: FP64 diffusion");
     using L = Lds<Q>;
@@ -357,11 +377,13 @@ k_apply(const T *__restrict__ bas, const int nex, const int ney, const int nvec,
     T *const s0 = reinterpret_cast<T *>(smem_raw);
     T *const s1 = s0 + GV * L::BUF;
     T *const s2 = s1 + GV * L::BUF;
+    T *const s3 = s2 + GV * L::BUF;  // split stages only
     // OTF: element vertices [G][8][3], 1D rule x [Q], w [Q] (one contiguous run), Jacobian columns [G][3][Q^2][3]
-    double *const sV = reinterpret_cast<double *>(s2 + GV * L::BUF);
+    double *const sV = reinterpret_cast<double *>(SPLIT ? s3 + GV * L::BUF : s2 + GV * L::BUF);
     double *const sR = sV + G * 24;
     double *const sJ = sR + 2 * Q;
     const int tid = threadIdx.x;
+    const int half = tid / NT2, lane = tid - half * NT2;  // split stages: wave-uniform halves
     const GroupPos gpos = group_pos<G>(xcd_block(blockIdx.x, gridDim.x), nex);
     const int64_t e0 = gpos.e0;
     const int nvalid = gpos.nvalid;
@@ -447,14 +469,40 @@ k_apply(const T *__restrict__ bas, const int nex, const int ney, const int nvec,
                         for (int d = 0; d < 3; ++d) sJ[3 * t + d] = j[d];
                     }
                 }
-                gather_store<P, Q, G, NT, VC>(s0, xv, off, nvec, v0, nvalid, tid);
+                gather_store<P, Q, G, NT, VC>(SPLIT && COLLOC ? s3 : s0, xv, off, nvec, v0, nvalid, tid);
             } else {
-                gather<P, Q, G, NT, VC, T>(s0, off, x, nvec, v0, nvalid, tid);
+                gather<P, Q, G, NT, VC, T>(SPLIT && COLLOC ? s3 : s0, off, x, nvec, v0, nvalid, tid);
             }
             group_sync<NT>();
-            interp<P, Q, COLLOC, GV, NT, T>(s0, bas, tid);
-            {
+            if constexpr (SPLIT) {
+                // nodes (s0) -> points (s3), ping-ponging between s0 and s3
+                if constexpr (!COLLOC) {
+                    contract_halves<0, P, P, P, Q, NT2, Q, 1>(s0, s3, bas + basis_bf(P, Q), half, lane);
+                    group_sync<NT>();
+                    contract_halves<1, Q, P, P, Q, NT2, Q, 1>(s3, s0, bas + basis_bf(P, Q), half, lane);
+                    group_sync<NT>();
+                    contract_halves<2, Q, Q, P, Q, NT2, Q, 1>(s0, s3, bas + basis_bf(P, Q), half, lane);
+                    group_sync<NT>();
+                }
+                // gradient of s3: d/dr -> s1 and the first d/dt rows -> s0 (half 0), d/ds -> s2 and the
+                // other d/dt rows (half 1)
+                constexpr int NQH = (Q + 1) / 2;
+                if (half == 0) {
+                    contract<0, Q, Q, Q, Q, 1, NT2, Q, -1>(s3, s1, bas + basis_df(P, Q), lane);
+                    contract<2, Q, Q, Q, Q, 1, NT2, Q, -1, T, false, 0, NQH / 2>(s3, s0, bas + basis_df(P, Q), lane);
+                } else {
+                    contract<1, Q, Q, Q, Q, 1, NT2, Q, -1>(s3, s2, bas + basis_df(P, Q), lane);
+                    contract<2, Q, Q, Q, Q, 1, NT2, Q, -1, T, false, NQH / 2, NQH>(s3, s0, bas + basis_df(P, Q),
+                                                                                     lane);
+                }
+                group_sync<NT>();
+            } else {
+                interp<P, Q, COLLOC, GV, NT, T>(s0, bas, tid);
                 grad<P, Q, GV, NT, T>(s0, s1, s2, bas, tid);
+            }
+            {
+                // split stages write d/dt's factor product to s3 (s0 is the transposed gradient's output)
+                T *const st = SPLIT ? s3 : s0;
 #pragma unroll
                 for (int k = 0; k < RQ; ++k) {
                     const int id = tid + k * NT;
@@ -479,30 +527,51 @@ k_apply(const T *__restrict__ bas, const int nex, const int ney, const int nvec,
                             const T ur = s1[ls], us = s2[ls], ut = s0[ls];
                             s1[ls] = gm[0] * ur + gm[5] * us + gm[4] * ut;
                             s2[ls] = gm[5] * ur + gm[1] * us + gm[3] * ut;
-                            s0[ls] = gm[4] * ur + gm[3] * us + gm[2] * ut;
+                            st[ls] = gm[4] * ur + gm[3] * us + gm[2] * ut;
                         }
                     }
                 }
                 group_sync<NT>();
-                // transposed gradient: x and y lines in place, then the z lines
-                // of s0 with the x and y parts added
-                contract<0, Q, Q, Q, Q, GV, NT, Q, -1>(s1, s1, bas + basis_dtf(P, Q), tid);
-                contract<1, Q, Q, Q, Q, GV, NT, Q, -1>(s2, s2, bas + basis_dtf(P, Q), tid);
-                group_sync<NT>();
-                contract<2, Q, Q, Q, Q, GV, NT, Q, -1, T, true>(s0, s0, bas + basis_dtf(P, Q), tid, s1, s2);
-                // same lines, same lanes: B^T along z follows without a sync
+                if constexpr (SPLIT) {
+                    // transposed gradient: x lines of s1 (half 0) and y lines of s2 (half 1) in place,
+                    // then the z lines of s3 with both added, into s0, shared by the halves
+                    if (half == 0) contract<0, Q, Q, Q, Q, 1, NT2, Q, -1>(s1, s1, bas + basis_dtf(P, Q), lane);
+                    else contract<1, Q, Q, Q, Q, 1, NT2, Q, -1>(s2, s2, bas + basis_dtf(P, Q), lane);
+                    group_sync<NT>();
+                    contract_halves<2, Q, Q, Q, Q, NT2, Q, -1, T, true>(s3, s0, bas + basis_dtf(P, Q), half, lane,
+                                                                          s1, s2);
+                    if constexpr (!COLLOC) group_sync<NT>();
+                } else {
+                    // transposed gradient: x and y lines in place, then the z lines
+                    // of s0 with the x and y parts added
+                    contract<0, Q, Q, Q, Q, GV, NT, Q, -1>(s1, s1, bas + basis_dtf(P, Q), tid);
+                    contract<1, Q, Q, Q, Q, GV, NT, Q, -1>(s2, s2, bas + basis_dtf(P, Q), tid);
+                    group_sync<NT>();
+                    contract<2, Q, Q, Q, Q, GV, NT, Q, -1, T, true>(s0, s0, bas + basis_dtf(P, Q), tid, s1, s2);
+                    // same lines, same lanes: B^T along z follows without a sync
+                }
             }
         }
         // transposed interpolation back to the nodes
+        T *sout = s0;
         if constexpr (!COLLOC) {
-            contract<2, Q, Q, Q, P, GV, NT, Q, 1>(s0, s0, bas + basis_btf(P, Q), tid);
-            group_sync<NT>();
-            contract<1, Q, Q, P, P, GV, NT, Q, 1>(s0, s0, bas + basis_btf(P, Q), tid);
-            group_sync<NT>();
-            contract<0, Q, P, P, P, GV, NT, Q, 1>(s0, s0, bas + basis_btf(P, Q), tid);
+            if constexpr (SPLIT) {
+                contract_halves<2, Q, Q, Q, P, NT2, Q, 1>(s0, s3, bas + basis_btf(P, Q), half, lane);
+                group_sync<NT>();
+                contract_halves<1, Q, Q, P, P, NT2, Q, 1>(s3, s0, bas + basis_btf(P, Q), half, lane);
+                group_sync<NT>();
+                contract_halves<0, Q, P, P, P, NT2, Q, 1>(s0, s3, bas + basis_btf(P, Q), half, lane);
+                sout = s3;
+            } else {
+                contract<2, Q, Q, Q, P, GV, NT, Q, 1>(s0, s0, bas + basis_btf(P, Q), tid);
+                group_sync<NT>();
+                contract<1, Q, Q, P, P, GV, NT, Q, 1>(s0, s0, bas + basis_btf(P, Q), tid);
+                group_sync<NT>();
+                contract<0, Q, P, P, P, GV, NT, Q, 1>(s0, s0, bas + basis_btf(P, Q), tid);
+            }
         }
         group_sync<NT>();
-        scatter_add<P, Q, G, NT, VC, T>(s0, off, y, nvec, v0, nvalid, tid);
+        scatter_add<P, Q, G, NT, VC, T>(sout, off, y, nvec, v0, nvalid, tid);
         group_sync<NT>();
     }
 }
