@@ -284,6 +284,64 @@ const char *mfhex_last_error(mfhex_op op);
  * derivative matrix of the tensor contractions.) */
 int mfhex_basis_1d(int p, int q, int quad, double *nodes, double *xq, double *wq, double *B, double *D);
 
+/* ---- Tetrahedral P_p diffusion: the non-tensor basis as a matrix product ----
+ * Sec. 3 (libCEED with its MAGMA / vendor-BLAS backend): a non-tensor basis
+ * is applied through its full matrices, the gradient matrix of one element
+ * (all quadrature points by all basis functions) times one column per
+ * element, i.e. one matrix product for all elements (batched along the
+ * elements).  Here 16 elements at a time go through the FP64 matrix cores,
+ * with the pointwise 3x3 factor applied to the products in registers and
+ * the transposed product back to the nodes in the same kernel.
+ *
+ * Mesh: the structured box of mfhex_desc (same vertex array, x fastest),
+ * every hexahedron split into the 6 Kuhn tetrahedra around its main
+ * diagonal, each affine on its 4 corner vertices.  Element e = 6 cube + t,
+ * cube = ex + nex (ey + ney ez).  Basis: Lagrange P_p (p = 1..6) on
+ * equispaced barycentric nodes; these are the points of the lattice of
+ * spacing h/p, so a vector has (p nex + 1)(p ney + 1)(p nez + 1) entries,
+ * numbered as in the hexahedral operator (x fastest).  Rule: collapsed
+ * Gauss-Jacobi, q points per direction (q = p or p+1; q = p integrates the
+ * stiffness of an affine element exactly), Q = q^3 points per element.
+ * y = A x with A = sum_e P_e^T K_e P_e, K_e the element stiffness; with
+ * dirichlet = 1 the box-boundary nodes are masked (y = 0 there, x ignored). */
+typedef struct mfhex_tet_s *mfhex_tet;
+
+typedef struct {
+    int32_t nex, ney, nez, p, q, dirichlet;
+    const double *vertex_xyz; /* HOST [(nex+1)(ney+1)(nez+1)][3]; read during mfhex_tet_create only */
+} mfhex_tet_desc;
+
+typedef struct {
+    int64_t n_nodes, n_elem, n_qpts;
+    size_t workspace_bytes; /* device bytes the caller provides (256-byte aligned) */
+    int32_t n_basis, n_points;  /* per element: (p+1)(p+2)(p+3)/6 and q^3 */
+} mfhex_tet_sizes;
+
+/* Sizes of an operator (host only).  ERR_UNSUPPORTED for p outside 1..6 or
+ * q not in {p, p+1}. */
+int mfhex_tet_query(const mfhex_tet_desc *d, mfhex_tet_sizes *out);
+
+/* Build the operator in the caller's workspace (basis-gradient fragments,
+ * element restriction, per-point factors w |det J| J^-1 J^-T).  Synchronizes
+ * `stream`; ERR_MESH for a degenerate tetrahedron.  The workspace must
+ * outlive the handle; the library owns only host metadata. */
+int mfhex_tet_create(const mfhex_tet_desc *d, void *workspace_dev, size_t workspace_bytes, void *stream,
+                     mfhex_tet *out);
+
+/* y = A x, FP64 device vectors [n_nodes], distinct.  Asynchronous on `stream`
+ * (y is zeroed first, then summed with atomics). */
+int mfhex_tet_apply(mfhex_tet op, const double *x_dev, double *y_dev, void *stream);
+
+int mfhex_tet_destroy(mfhex_tet op);
+
+/* The library's reference tables (host only, no device work): rule points
+ * xi [q^3][3] and weights w [q^3] on the tetrahedron {xi >= 0, sum xi <= 1},
+ * basis values B [q^3][P] and reference gradients G [3][q^3][P] at the points,
+ * basis functions ordered by (n3, n2, n1) with n1 fastest, n the barycentric
+ * multi-index of the node.  Any output may be NULL.  Errors of the mfhex_tet
+ * calls are read with mfhex_last_error(NULL). */
+int mfhex_tet_basis(int p, int q, double *xi, double *w, double *B, double *G);
+
 /* Library version string. */
 const char *mfhex_version(void);
 

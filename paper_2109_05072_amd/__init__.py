@@ -3,7 +3,9 @@
 BP1 mass, BP3 / BP5 / BP6 diffusion by sum factorization in fused HIP
 kernels, CG (FP64 and FP32-operator mixed precision with FP64 residual
 replacement), the coefficient gradient behind a torch.autograd.Function,
-multi-RHS batching and an elements-per-block autotuner.  The C ABI is
+multi-RHS batching and an elements-per-block autotuner; a tetrahedral P_p
+diffusion operator whose non-tensor basis runs as matrix products on the FP64
+matrix cores.  The C ABI is
 include/mfhex.h; this package is its Python binding.
 """
 from ._lib import (EXPORTS, MFHexError, load, mfhex_version,  # noqa: F401
@@ -17,6 +19,9 @@ def __getattr__(name):
     if name == "Operator":
         from .operator import Operator
         return Operator
+    if name == "TetOperator":
+        from .tet import TetOperator
+        return TetOperator
     if name == "CGResult":
         from .operator import CGResult
         return CGResult

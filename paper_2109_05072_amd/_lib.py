@@ -35,6 +35,7 @@ EXPORTS = (
     "mfhex_cg", "mfhex_tune", "mfhex_get_config", "mfhex_set_config", "mfhex_diagonal", "mfhex_mg_query", "mfhex_mg_setup",
     "mfhex_mg_apply", "mfhex_mg_level", "mfhex_strerror", "mfhex_last_error",
     "mfhex_basis_1d", "mfhex_version",
+    "mfhex_tet_query", "mfhex_tet_create", "mfhex_tet_apply", "mfhex_tet_destroy", "mfhex_tet_basis",
 )
 
 
@@ -65,6 +66,16 @@ class mfhex_mg_opts(C.Structure):
     _fields_ = [("degree", C.c_int32), ("coarse_degree", C.c_int32), ("power_iters", C.c_int32),
                 ("max_levels", C.c_int32), ("precision", C.c_int32), ("pad_", C.c_int32), ("lo", C.c_double),
                 ("hi", C.c_double)]
+
+
+class mfhex_tet_desc(C.Structure):
+    _fields_ = [("nex", C.c_int32), ("ney", C.c_int32), ("nez", C.c_int32), ("p", C.c_int32), ("q", C.c_int32),
+                ("dirichlet", C.c_int32), ("vertex_xyz", C.POINTER(C.c_double))]
+
+
+class mfhex_tet_sizes(C.Structure):
+    _fields_ = [("n_nodes", C.c_int64), ("n_elem", C.c_int64), ("n_qpts", C.c_int64),
+                ("workspace_bytes", C.c_size_t), ("n_basis", C.c_int32), ("n_points", C.c_int32)]
 
 
 class mfhex_cg_stats(C.Structure):
@@ -121,6 +132,11 @@ def load(path: str = LIB_PATH):
         "mfhex_last_error": ([vp], C.c_char_p),
         "mfhex_basis_1d": ([i32, i32, i32] + [C.POINTER(C.c_double)] * 5, i32),
         "mfhex_version": ([], C.c_char_p),
+        "mfhex_tet_query": ([C.POINTER(mfhex_tet_desc), C.POINTER(mfhex_tet_sizes)], i32),
+        "mfhex_tet_create": ([C.POINTER(mfhex_tet_desc), vp, sz, vp, C.POINTER(vp)], i32),
+        "mfhex_tet_apply": ([vp, vp, vp, vp], i32),
+        "mfhex_tet_destroy": ([vp], i32),
+        "mfhex_tet_basis": ([i32, i32] + [C.POINTER(C.c_double)] * 4, i32),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -250,6 +266,36 @@ def mfhex_basis_1d(p: int, q: int, quad: int):
     out = [np.zeros(P), np.zeros(q), np.zeros(q), np.zeros((q, P)), np.zeros((q, q))]
     ptrs = [a.ctypes.data_as(C.POINTER(C.c_double)) for a in out]
     check(load().mfhex_basis_1d(p, q, quad, *ptrs))
+    return tuple(out)
+
+
+def mfhex_tet_query(desc: mfhex_tet_desc) -> mfhex_tet_sizes:
+    s = mfhex_tet_sizes()
+    check(load().mfhex_tet_query(C.byref(desc), C.byref(s)))
+    return s
+
+
+def mfhex_tet_create(desc: mfhex_tet_desc, work: int, nbytes: int, stream: int) -> int:
+    h = C.c_void_p()
+    check(load().mfhex_tet_create(C.byref(desc), work, nbytes, stream, C.byref(h)))
+    return h.value
+
+
+def mfhex_tet_apply(op: int, x: int, y: int, stream: int) -> None:
+    check(load().mfhex_tet_apply(op, x, y, stream))
+
+
+def mfhex_tet_destroy(op: int) -> None:
+    check(load().mfhex_tet_destroy(op))
+
+
+def mfhex_tet_basis(p: int, q: int):
+    """(xi [Q,3], w [Q], B [Q,P], G [3,Q,P]) from the library's host set-up code."""
+    import numpy as np
+    Q, P = q ** 3, (p + 1) * (p + 2) * (p + 3) // 6
+    out = [np.zeros((Q, 3)), np.zeros(Q), np.zeros((Q, P)), np.zeros((3, Q, P))]
+    ptrs = [a.ctypes.data_as(C.POINTER(C.c_double)) for a in out]
+    check(load().mfhex_tet_basis(p, q, *ptrs))
     return tuple(out)
 
 

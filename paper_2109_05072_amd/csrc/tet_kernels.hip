@@ -1,0 +1,258 @@
+// Tetrahedral P_p diffusion operator: set-up and fused apply kernels.
+//
+// Apply (Sec. 3: the non-tensor basis action as a matrix product over
+// elements).  One wavefront owns 16 elements.  For each block of 16
+// quadrature points b:
+//   phase 1, U_d = G_d X on the FP64 matrix cores: A = the basis-gradient rows
+//     of the block (16 points x 4 basis functions per step, a pre-swizzled
+//     fragment: one contiguous 512-byte load), B = the 16 elements' gathered
+//     values (4 basis functions x 16 elements per step, kept in registers for
+//     the whole element group);
+//   pointwise, in the result registers: v = D_q u with the symmetric factor
+//     D_q = w |det J| J^-1 J^-T of each (point, element);
+//   phase 2, Y^T += V_d^T G_d: result register r of every lane holds the
+//     points 16b + 4r + (0..3) of one element (the matrix-core result
+//     layout), which is exactly the A operand of a 4-deep step over those
+//     points, so the products feed the transposed contraction with no data
+//     movement; B = the gradient rows of the same 4 points (pre-swizzled).
+// The 16 x P element results then go to the nodes with FP64 atomics.
+#include "mfhex_internal.h"
+#include "tet.h"
+
+namespace mfhex {
+namespace tet {
+
+namespace {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ d4 mma(double a, double b, d4 c)
+{
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// Kuhn tetrahedron t: axis permutation; vertex k is the cube corner sum_{m<k} e_{pi[m]}.
+__device__ __forceinline__ void kuhn_perm(int t, int &a0, int &a1, int &a2)
+{
+    const int perms[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
+    a0 = perms[t][0];
+    a1 = perms[t][1];
+    a2 = perms[t][2];
+}
+
+// Blocks are dealt to the 8 XCDs round-robin; give each XCD a contiguous range of element groups.
+__device__ __forceinline__ int64_t xcd_remap(int64_t bid, int64_t nb)
+{
+    const int64_t x = bid % kNumXcd, i = bid / kNumXcd;
+    const int64_t q = nb / kNumXcd, r = nb % kNumXcd;
+    return x * q + (x < r ? x : r) + i;
+}
+
+// offsets[g][n][16]: global lattice node of basis function n of element 16 g + j (-1: masked / none).
+__global__ void k_tet_offsets(int p, int P, int nex, int ney, int nez, int dirichlet, int64_t nelem, int64_t total,
+                              const int32_t *__restrict__ lattice, int32_t *__restrict__ offsets)
+{
+    const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (idx >= total) return;
+    const int j = (int)(idx % kGroup);
+    const int n = (int)((idx / kGroup) % P);
+    const int64_t e = (idx / ((int64_t)kGroup * P)) * kGroup + j;
+    int32_t o = -1;
+    if (e < nelem) {
+        const int64_t cube = e / 6;
+        const int t = (int)(e % 6);
+        const int ex = (int)(cube % nex), ey = (int)((cube / nex) % ney), ez = (int)(cube / ((int64_t)nex * ney));
+        int a0, a1, a2;
+        kuhn_perm(t, a0, a1, a2);
+        const int n1 = lattice[4 * n], n2 = lattice[4 * n + 1], n3 = lattice[4 * n + 2];
+        // lattice offset n1 v1 + n2 v2 + n3 v3 with v1 = e_a0, v2 = e_a0 + e_a1, v3 = (1,1,1)
+        int a[3] = {n3, n3, n3};
+        a[a0] += n1 + n2;
+        a[a1] += n2;
+        (void)a2;
+        const int nx = p * nex + 1, ny = p * ney + 1, nz = p * nez + 1;
+        const int I = p * ex + a[0], J = p * ey + a[1], K = p * ez + a[2];
+        const bool bnd = I == 0 || I == nx - 1 || J == 0 || J == ny - 1 || K == 0 || K == nz - 1;
+        if (!(dirichlet && bnd)) o = I + nx * (J + ny * K);
+    }
+    offsets[idx] = o;
+}
+
+// qdata[g][m][6][16] = w_m |det J| J^-1 J^-T = w_m adj(J) adj(J)^T / |det J| (xx, yy, zz, yz, xz, xy).
+__global__ void k_tet_qdata(int Q, int nex, int ney, int64_t nelem, int64_t nslots, const double *__restrict__ vert,
+                            const double *__restrict__ wq, double *__restrict__ qdata, int *__restrict__ bad)
+{
+    const int64_t slot = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (slot >= nslots) return;
+    const int64_t g = slot / kGroup;
+    const int j = (int)(slot % kGroup);
+    const int64_t e = slot;
+    double M[6] = {0, 0, 0, 0, 0, 0};
+    if (e < nelem) {
+        const int64_t cube = e / 6;
+        const int t = (int)(e % 6);
+        const int ex = (int)(cube % nex), ey = (int)((cube / nex) % ney), ez = (int)(cube / ((int64_t)nex * ney));
+        int a0, a1, a2;
+        kuhn_perm(t, a0, a1, a2);
+        int c[4][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}, {1, 1, 1}};
+        c[1][a0] = 1;
+        c[2][a0] = 1;
+        c[2][a1] = 1;
+        (void)a2;
+        double X[4][3];
+        for (int v = 0; v < 4; ++v) {
+            const int64_t vid = (ex + c[v][0]) + (int64_t)(nex + 1) * ((ey + c[v][1]) + (int64_t)(ney + 1) * (ez + c[v][2]));
+            for (int d = 0; d < 3; ++d) X[v][d] = vert[3 * vid + d];
+        }
+        double Jm[3][3];  // J[row = physical dir][col = reference dir]
+        for (int r = 0; r < 3; ++r)
+            for (int cc = 0; cc < 3; ++cc) Jm[r][cc] = X[cc + 1][r] - X[0][r];
+        // adjugate: adj(J)[i][k] = cofactor(J)[k][i]
+        double A[3][3];
+        for (int i = 0; i < 3; ++i)
+            for (int k = 0; k < 3; ++k) {
+                const int r0 = (k + 1) % 3, r1 = (k + 2) % 3, c0 = (i + 1) % 3, c1 = (i + 2) % 3;
+                A[i][k] = Jm[r0][c0] * Jm[r1][c1] - Jm[r0][c1] * Jm[r1][c0];
+            }
+        const double det = Jm[0][0] * A[0][0] + Jm[0][1] * A[1][0] + Jm[0][2] * A[2][0];
+        if (!(det != 0.0) || !isfinite(det)) bad[0] = 1;
+        const double s = 1.0 / fabs(det);
+        // (adj adj^T)[a][b] = sum_i adj[a][i] adj[b][i]
+        auto aa = [&](int x, int y) { return (A[x][0] * A[y][0] + A[x][1] * A[y][1] + A[x][2] * A[y][2]) * s; };
+        M[0] = aa(0, 0);
+        M[1] = aa(1, 1);
+        M[2] = aa(2, 2);
+        M[3] = aa(1, 2);
+        M[4] = aa(0, 2);
+        M[5] = aa(0, 1);
+    }
+    double *qd = qdata + (size_t)g * Q * 6 * kGroup + j;
+    for (int m = 0; m < Q; ++m) {
+        const double w = wq[m];
+        for (int f = 0; f < 6; ++f) qd[((size_t)m * 6 + f) * kGroup] = w * M[f];
+    }
+}
+
+template <int p, int q>
+__global__ void __launch_bounds__(64 * kWaves)
+k_tet_apply(int64_t ngroups, const double *__restrict__ afrag, const double *__restrict__ bfrag,
+            const int32_t *__restrict__ offsets, const double *__restrict__ qdata, const double *__restrict__ x,
+            double *__restrict__ y)
+{
+    constexpr Dims D = dims(p, q);
+    constexpr int P = D.P, Q = D.Q, NS = D.Pk / 4, NT = D.Pn / 16, NB = D.Qp / 16;
+    const int lane = threadIdx.x & 63;
+    const int64_t g = xcd_remap(blockIdx.x, gridDim.x) * kWaves + threadIdx.x / 64;  // wavefront-uniform
+    if (g >= ngroups) return;
+    const int el = lane % 16, kq = lane / 16;
+    const int32_t *off = offsets + (size_t)g * P * kGroup;
+
+    // B operand of phase 1: lane holds X[basis 4s + kq][element el] for every step s
+    double xf[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        const int n = 4 * s + kq;
+        const int32_t o = n < P ? off[n * kGroup + el] : -1;
+        xf[s] = o >= 0 ? x[o] : 0.0;
+    }
+    d4 yacc[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) yacc[t] = d4{0.0, 0.0, 0.0, 0.0};
+
+    const double *qg = qdata + (size_t)g * Q * 6 * kGroup + el;
+    for (int b = 0; b < NB; ++b) {
+        const double *A = afrag + (size_t)b * 3 * NS * 64 + lane;
+        d4 u[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) u[d] = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int s = 0; s < NS; ++s)
+#pragma unroll
+            for (int d = 0; d < 3; ++d) u[d] = mma(A[(d * NS + s) * 64], xf[s], u[d]);
+        // pointwise: register r <-> point 16 b + 4 r + kq of element el
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int m = 16 * b + 4 * r + kq;
+            double v0 = 0.0, v1 = 0.0, v2 = 0.0;
+            if (m < Q) {
+                const double *qd = qg + (size_t)m * 6 * kGroup;
+                const double xx = qd[0], yy = qd[kGroup], zz = qd[2 * kGroup], yz = qd[3 * kGroup],
+                             xz = qd[4 * kGroup], xy = qd[5 * kGroup];
+                const double ur = u[0][r], us = u[1][r], ut = u[2][r];
+                v0 = xx * ur + xy * us + xz * ut;
+                v1 = xy * ur + yy * us + yz * ut;
+                v2 = xz * ur + yz * us + zz * ut;
+            }
+            u[0][r] = v0;
+            u[1][r] = v1;
+            u[2][r] = v2;
+        }
+        const double *Bf = bfrag + (size_t)b * 3 * 4 * NT * 64 + lane;
+#pragma unroll
+        for (int d = 0; d < 3; ++d)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+#pragma unroll
+                for (int t = 0; t < NT; ++t) yacc[t] = mma(u[d][r], Bf[((d * 4 + r) * NT + t) * 64], yacc[t]);
+    }
+    // result register r of tile t: element 4 r + kq, basis function 16 t + el
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+        const int n = 16 * t + el;
+        if (n < P) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int32_t o = off[n * kGroup + 4 * r + kq];
+                if (o >= 0) unsafeAtomicAdd(&y[o], yacc[t][r]);
+            }
+        }
+    }
+}
+
+template <int p, int q>
+hipError_t apply_pq(const TetLaunch &a)
+{
+    const int64_t nblk = (a.ngroups + kWaves - 1) / kWaves;
+    hipLaunchKernelGGL((k_tet_apply<p, q>), dim3((unsigned)nblk), dim3(64 * kWaves), 0, a.stream, a.ngroups, a.afrag,
+                       a.bfrag, a.offsets, a.qdata, a.x, a.y);
+    return hipGetLastError();
+}
+
+template <int p>
+hipError_t apply_p(const TetLaunch &a)
+{
+    if (a.q == p) return apply_pq<p, p>(a);
+    if (a.q == p + 1) return apply_pq<p, p + 1>(a);
+    return hipErrorInvalidValue;
+}
+
+}  // namespace
+
+hipError_t launch_tet_setup(const TetSetupLaunch &s)
+{
+    const int P = n_basis(s.p), Q = s.q * s.q * s.q;
+    const int64_t total = s.ngroups * P * kGroup, nslots = s.ngroups * kGroup;
+    hipLaunchKernelGGL(k_tet_offsets, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s.stream, s.p, P, s.nex,
+                       s.ney, s.nez, s.dirichlet, s.nelem, total, s.lattice, s.offsets);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_tet_qdata, dim3((unsigned)((nslots + 127) / 128)), dim3(128), 0, s.stream, Q, s.nex, s.ney,
+                       s.nelem, nslots, s.vert, s.wq, s.qdata, s.bad);
+    return hipGetLastError();
+}
+
+hipError_t launch_tet_apply(const TetLaunch &a)
+{
+    switch (a.p) {
+    case 1: return apply_p<1>(a);
+    case 2: return apply_p<2>(a);
+    case 3: return apply_p<3>(a);
+    case 4: return apply_p<4>(a);
+    case 5: return apply_p<5>(a);
+    case 6: return apply_p<6>(a);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace tet
+}  // namespace mfhex
