@@ -100,6 +100,8 @@ def main():
                     help="also time the variable-coefficient forward / backward (p=4, 1e7 DOFs)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cg", action="store_true", help="also time FP64 vs mixed CG to 1e-10")
+    ap.add_argument("--tet", action="store_true",
+                    help="also time the tetrahedral P_p diffusion apply (matrix-core basis products), p=2..6")
     ap.add_argument("--tune", action="store_true", help="autotune the launch variant before timing")
     ap.add_argument("--otf", action="store_true",
                     help="diffusion with the geometric factors evaluated in the kernel (no stored factors)")
@@ -230,6 +232,8 @@ def main():
         out["cg"] = cg_compare()
     if args.batched:
         out["batched"] = batched_sweep()
+    if args.tet:
+        out["tet"] = tet_bench()
     if args.adjoint:
         out["adjoint"] = adjoint_bench()
     if not args.no_cpu_baseline:
@@ -390,6 +394,54 @@ def adjoint_bench(p=4, dofs=1e7):
            "backward_ms": round(bwd_ms, 3), "kappa_grad_ms": round(kg_ms, 3), "fd_checks": fd}
     op.close()
     return out
+
+
+def tet_dims(p: int, q: int):
+    P, Q = (p + 1) * (p + 2) * (p + 3) // 6, q ** 3
+    r = lambda n, m: (n + m - 1) // m * m
+    return P, Q, r(Q, 16), r(P, 4), r(P, 16)
+
+
+def tet_bench(orders=(2, 3, 4, 5, 6), dofs=1e7, reps=20):
+    """Tetrahedral P_p apply at about `dofs` nodes per order (Kuhn split of the perturbed box)."""
+    import torch
+    import synth
+    import paper_2109_05072_amd as mf
+    res = []
+    for p in orders:
+        ne = synth.elems_for_dofs(dofs, p)
+        op = mf.TetOperator(ne, ne, ne, p, synth.mesh_vertices(ne, ne, ne))
+        x = torch.from_numpy(synth.uniform_vector(op.n_nodes)).cuda()
+        y = torch.empty_like(x)
+        for _ in range(3):
+            op.apply(x, y)
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+        for e0, e1 in ev:
+            e0.record()
+            op.apply(x, y)
+            e1.record()
+        torch.cuda.synchronize()
+        ms = float(np.median([a.elapsed_time(b) for a, b in ev]))
+        P, Q, Qp, Pk, Pn = tet_dims(p, op.q)
+        E, N = op.n_elem, op.n_nodes
+        useful = E * (12.0 * Q * P + 15.0 * Q)          # two products of 3Q x P per element + the 3x3 per point
+        groups = -(-E // 16)
+        issued = groups * 2048.0 * (3 * (Qp // 16) * (Pk // 4) + 12 * (Qp // 16) * (Pn // 16))
+        byts = 8 * N + 8 * N + 4 * E * P + 48 * E * Q
+        t = ms / 1e3
+        r = {"p": p, "q": op.q, "elements": E, "dofs": N, "basis_per_elem": P, "points_per_elem": Q, "ms": round(ms, 4),
+             "gdofs": round(N / t / 1e9, 3), "useful_tflops": round(useful / t / 1e12, 2),
+             "mfma_frac_useful": round(useful / t / 1e12 / FP64_PEAK_TFLOPS, 4),
+             "issued_mfma_tflops": round(issued / t / 1e12, 2),
+             "mfma_frac_issued": round(issued / t / 1e12 / FP64_PEAK_TFLOPS, 4),
+             "alg_bytes": byts, "alg_gbs": round(byts / t / 1e9, 1), "hbm_frac": round(byts / t / 1e9 / HBM_PEAK_GBS, 4),
+             "flop_per_byte": round(useful / byts, 2)}
+        res.append(r)
+        print(f"# tet {r}", file=sys.stderr, flush=True)
+        op.close()
+        del op, x, y
+        torch.cuda.empty_cache()
+    return res
 
 
 def cg_compare(orders=(3, 5, 7), dofs=3e7):

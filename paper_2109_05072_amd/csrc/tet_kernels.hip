@@ -1,11 +1,13 @@
 // Tetrahedral P_p diffusion operator: set-up and fused apply kernels.
 //
 // Apply (Sec. 3: the non-tensor basis action as a matrix product over
-// elements).  One wavefront owns 16 elements.  For each block of 16
-// quadrature points b:
+// elements).  One wavefront owns 16 elements; the kWaves wavefronts of a
+// thread group stage the basis fragments of each block of 16 quadrature
+// points b in LDS together (coalesced copies shared by 4 x 16 elements,
+// fetched one phase ahead), then each:
 //   phase 1, U_d = G_d X on the FP64 matrix cores: A = the basis-gradient rows
 //     of the block (16 points x 4 basis functions per step, a pre-swizzled
-//     fragment: one contiguous 512-byte load), B = the 16 elements' gathered
+//     fragment of 64 consecutive doubles), B = the 16 elements' gathered
 //     values (4 basis functions x 16 elements per step, kept in registers for
 //     the whole element group);
 //   pointwise, in the result registers: v = D_q u with the symmetric factor
@@ -133,6 +135,9 @@ __global__ void k_tet_qdata(int Q, int nex, int ney, int64_t nelem, int64_t nslo
     }
 }
 
+// LDS: the gradient fragments of one point block, shared by the kWaves element groups of the thread group.
+constexpr size_t frag_block_doubles(const Dims &D) { return (size_t)3 * (D.Pk / 4) * 64 + (size_t)12 * (D.Pn / 16) * 64; }
+
 template <int p, int q>
 __global__ void __launch_bounds__(64 * kWaves)
 k_tet_apply(int64_t ngroups, const double *__restrict__ afrag, const double *__restrict__ bfrag,
@@ -141,9 +146,14 @@ k_tet_apply(int64_t ngroups, const double *__restrict__ afrag, const double *__r
 {
     constexpr Dims D = dims(p, q);
     constexpr int P = D.P, Q = D.Q, NS = D.Pk / 4, NT = D.Pn / 16, NB = D.Qp / 16;
+    constexpr int AL = 3 * NS * 64, BL = 12 * NT * 64, FL = AL + BL;
+    extern __shared__ __align__(16) double sfrag[];
     const int lane = threadIdx.x & 63;
-    const int64_t g = xcd_remap(blockIdx.x, gridDim.x) * kWaves + threadIdx.x / 64;  // wavefront-uniform
-    if (g >= ngroups) return;
+    const int64_t g0 = xcd_remap(blockIdx.x, gridDim.x) * kWaves + threadIdx.x / 64;  // wavefront-uniform
+    // every wavefront takes part in the staging and its barriers; one past the last group computes on
+    // the last group's data and stores nothing
+    const bool active = g0 < ngroups;
+    const int64_t g = active ? g0 : ngroups - 1;
     const int el = lane % 16, kq = lane / 16;
     const int32_t *off = offsets + (size_t)g * P * kGroup;
 
@@ -160,8 +170,32 @@ k_tet_apply(int64_t ngroups, const double *__restrict__ afrag, const double *__r
     for (int t = 0; t < NT; ++t) yacc[t] = d4{0.0, 0.0, 0.0, 0.0};
 
     const double *qg = qdata + (size_t)g * Q * 6 * kGroup + el;
+    // staging is software-pipelined: the B fragments of block b travel (global -> registers) during
+    // phase 1, the A fragments of block b+1 during phase 2; each lands in LDS at the next barrier
+    constexpr int NTH = 64 * kWaves, RA = (AL + NTH - 1) / NTH, RB = (BL + NTH - 1) / NTH;
+    double *const sA = sfrag, *const sB = sfrag + AL;
+    const int tid = threadIdx.x;
+    double stage[RA > RB ? RA : RB];
+#pragma unroll
+    for (int k = 0; k < RA; ++k)
+        if (tid + k * NTH < AL) sA[tid + k * NTH] = afrag[tid + k * NTH];
+    __syncthreads();
     for (int b = 0; b < NB; ++b) {
-        const double *A = afrag + (size_t)b * 3 * NS * 64 + lane;
+        // this lane's factors for the block (issued first: their latency overlaps phase 1)
+        double qv[4][6];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int m = 16 * b + 4 * r + kq;
+            const double *qd = qg + (size_t)(m < Q ? m : Q - 1) * 6 * kGroup;
+#pragma unroll
+            for (int f = 0; f < 6; ++f) qv[r][f] = m < Q ? qd[f * kGroup] : 0.0;
+        }
+        {
+            const double *bb = bfrag + (size_t)b * BL;
+#pragma unroll
+            for (int k = 0; k < RB; ++k) stage[k] = tid + k * NTH < BL ? bb[tid + k * NTH] : 0.0;
+        }
+        const double *A = sA + lane;
         d4 u[3];
 #pragma unroll
         for (int d = 0; d < 3; ++d) u[d] = d4{0.0, 0.0, 0.0, 0.0};
@@ -172,29 +206,36 @@ k_tet_apply(int64_t ngroups, const double *__restrict__ afrag, const double *__r
         // pointwise: register r <-> point 16 b + 4 r + kq of element el
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            const int m = 16 * b + 4 * r + kq;
-            double v0 = 0.0, v1 = 0.0, v2 = 0.0;
-            if (m < Q) {
-                const double *qd = qg + (size_t)m * 6 * kGroup;
-                const double xx = qd[0], yy = qd[kGroup], zz = qd[2 * kGroup], yz = qd[3 * kGroup],
-                             xz = qd[4 * kGroup], xy = qd[5 * kGroup];
-                const double ur = u[0][r], us = u[1][r], ut = u[2][r];
-                v0 = xx * ur + xy * us + xz * ut;
-                v1 = xy * ur + yy * us + yz * ut;
-                v2 = xz * ur + yz * us + zz * ut;
-            }
-            u[0][r] = v0;
-            u[1][r] = v1;
-            u[2][r] = v2;
+            const double xx = qv[r][0], yy = qv[r][1], zz = qv[r][2], yz = qv[r][3], xz = qv[r][4], xy = qv[r][5];
+            const double ur = u[0][r], us = u[1][r], ut = u[2][r];
+            u[0][r] = xx * ur + xy * us + xz * ut;
+            u[1][r] = xy * ur + yy * us + yz * ut;
+            u[2][r] = xz * ur + yz * us + zz * ut;
         }
-        const double *Bf = bfrag + (size_t)b * 3 * 4 * NT * 64 + lane;
+#pragma unroll
+        for (int k = 0; k < RB; ++k)
+            if (tid + k * NTH < BL) sB[tid + k * NTH] = stage[k];
+        __syncthreads();  // B fragments of b in LDS; every wavefront is done with the A fragments of b
+        if (b + 1 < NB) {
+            const double *ab = afrag + (size_t)(b + 1) * AL;
+#pragma unroll
+            for (int k = 0; k < RA; ++k) stage[k] = tid + k * NTH < AL ? ab[tid + k * NTH] : 0.0;
+        }
+        const double *Bf = sB + lane;
 #pragma unroll
         for (int d = 0; d < 3; ++d)
 #pragma unroll
             for (int r = 0; r < 4; ++r)
 #pragma unroll
                 for (int t = 0; t < NT; ++t) yacc[t] = mma(u[d][r], Bf[((d * 4 + r) * NT + t) * 64], yacc[t]);
+        if (b + 1 < NB) {
+#pragma unroll
+            for (int k = 0; k < RA; ++k)
+                if (tid + k * NTH < AL) sA[tid + k * NTH] = stage[k];
+        }
+        __syncthreads();  // A fragments of b+1 in LDS; every wavefront is done with the B fragments of b
     }
+    if (!active) return;
     // result register r of tile t: element 4 r + kq, basis function 16 t + el
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
@@ -213,8 +254,15 @@ template <int p, int q>
 hipError_t apply_pq(const TetLaunch &a)
 {
     const int64_t nblk = (a.ngroups + kWaves - 1) / kWaves;
-    hipLaunchKernelGGL((k_tet_apply<p, q>), dim3((unsigned)nblk), dim3(64 * kWaves), 0, a.stream, a.ngroups, a.afrag,
-                       a.bfrag, a.offsets, a.qdata, a.x, a.y);
+    const size_t lds = frag_block_doubles(dims(p, q)) * sizeof(double);
+    auto kern = k_tet_apply<p, q>;
+    if (lds > 65536) {
+        const hipError_t e =
+            hipFuncSetAttribute(reinterpret_cast<const void *>(kern), hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(kern, dim3((unsigned)nblk), dim3(64 * kWaves), lds, a.stream, a.ngroups, a.afrag, a.bfrag,
+                       a.offsets, a.qdata, a.x, a.y);
     return hipGetLastError();
 }
 
