@@ -15,8 +15,13 @@ roofline fraction uses the algorithmic bytes of one apply,
 over the measured duration, against 8 TB/s.  The CPU baseline times the FP64
 oracle (dense, no sum factorization) on a bounded sample on the host cores.
 
-Prints ONE JSON line.  Extra: --cg adds FP64 vs mixed-precision CG time to a
-1e-10 relative residual (not part of the timed step).
+The same run times a 1 GiB device copy and reports each order's fraction of
+that measured rate next to the datasheet fraction.
+
+Prints ONE JSON line.  Extras (not part of the timed step): --cg adds FP64 vs
+mixed-precision CG (and Jacobi / p-multigrid preconditioned CG) time to a
+1e-10 relative residual; --tet adds the tetrahedral P_p apply (matrix-core
+basis products, p = 2..6) with its FP64 MFMA and HBM fractions.
 """
 from __future__ import annotations
 

@@ -139,7 +139,7 @@ __global__ void k_tet_qdata(int Q, int nex, int ney, int64_t nelem, int64_t nslo
 constexpr size_t frag_block_doubles(const Dims &D) { return (size_t)3 * (D.Pk / 4) * 64 + (size_t)12 * (D.Pn / 16) * 64; }
 
 template <int p, int q>
-__global__ void __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(2)))
+__global__ void __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(p == 4 ? 3 : 2)))
 k_tet_apply(int64_t ngroups, const double *__restrict__ afrag, const double *__restrict__ bfrag,
             const int32_t *__restrict__ offsets, const double *__restrict__ qdata, const double *__restrict__ x,
             double *__restrict__ y)

@@ -1,7 +1,8 @@
 """Summaries of rocprofv3 output for the fused apply kernels.
 
 ``python -m paper_2109_05072_amd.prof_summary trace <dir> <command...>``
-    kernel-trace statistics (``*_kernel_stats.csv``) -> text table.
+    kernel-trace statistics (``*_kernel_stats.csv``) -> text table
+    (``trace-tet``: the same, hashed over the tetrahedral kernel sources).
 ``python -m paper_2109_05072_amd.prof_summary traffic <fetch_dir> <write_dir> <command...>``
     FETCH_SIZE / WRITE_SIZE per dispatch of each apply kernel, scaled by what
     the same counters read for the 1 GiB device-to-device copy that
@@ -25,12 +26,13 @@ from collections import defaultdict
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 KERNEL_SOURCES = ("csrc/apply_kernels.hpp", "csrc/mfhex_internal.h", "csrc/geom.hpp", "csrc/diag_kernels.hpp")
+TET_SOURCES = ("csrc/tet_kernels.hip", "csrc/tet.h")
 COPY_BYTES = 1 << 30
 
 
-def kernel_source_hash() -> str:
+def kernel_source_hash(sources=KERNEL_SOURCES) -> str:
     h = hashlib.sha256()
-    for rel in KERNEL_SOURCES:
+    for rel in sources:
         with open(os.path.join(HERE, rel), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
@@ -50,6 +52,9 @@ def _short(name: str) -> str:
         P, Q, colloc, T, G, NT, VC = m.groups()
         vc = f" VC={VC}" if VC != "1" else ""
         return f"k_mass p={int(P) - 1} q={Q} {T} G={G} NT={NT}{vc}"
+    m = re.match(r"void mfhex::tet::\(anonymous namespace\)::k_tet_apply<(\d+), (\d+)>", name)
+    if m:
+        return f"k_tet_apply p={m.group(1)} q={m.group(2)}"
     name = name.replace("(anonymous namespace)::", "").replace("void ", "")
     return name.split("(")[0].split("<")[0].split("::")[-1][:60]
 
@@ -61,10 +66,10 @@ def _find(d: str, suffix: str) -> str:
     return fs[0]
 
 
-def trace_summary(d: str, command: str) -> str:
+def trace_summary(d: str, command: str, sources=KERNEL_SOURCES) -> str:
     rows = list(csv.DictReader(open(_find(d, "kernel_stats.csv"))))
     out = [f"# rocprofv3 kernel trace summary", f"# command: {command}",
-           f"# kernel source hash: {kernel_source_hash()}",
+           f"# kernel source hash: {kernel_source_hash(sources)}",
            f"{'kernel':<60} {'calls':>6} {'avg_us':>10} {'min_us':>10} {'max_us':>10} {'pct':>6}"]
     for r in rows:
         out.append(f"{_short(r['Name']):<60} {int(r['Calls']):>6} {float(r['AverageNs']) / 1e3:>10.2f} "
@@ -130,6 +135,8 @@ if __name__ == "__main__":
     mode = sys.argv[1]
     if mode == "trace":
         sys.stdout.write(trace_summary(sys.argv[2], " ".join(sys.argv[3:])))
+    elif mode == "trace-tet":
+        sys.stdout.write(trace_summary(sys.argv[2], " ".join(sys.argv[3:]), TET_SOURCES))
     elif mode == "traffic":
         sys.stdout.write(traffic_summary(sys.argv[2], sys.argv[3], " ".join(sys.argv[4:])))
     else:
