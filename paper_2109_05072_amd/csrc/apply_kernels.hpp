@@ -757,6 +757,8 @@ static hipError_t launch_apply_v(const ApplyLaunch &a)
         const int64_t ngroups = (int64_t)a.v.ney * a.v.nez * ((a.v.nex + G - 1) / G);
         const int64_t nblk = (ngroups + chain - 1) / chain;
         auto kern = k_mass<P, Q, COLLOC, T, G, NT, VC>;
+        const hipError_t e = prepare_lds(kern, lds);
+        if (e != hipSuccess) return e;
         hipLaunchKernelGGL(kern, dim3((unsigned)nblk), dim3(NT), lds, a.stream, static_cast<const T *>(a.basis_dev),
                            a.v.nex, ngroups, a.nvec, chain, a.v.offsets, static_cast<const T *>(a.v.qdata),
                            static_cast<const T *>(a.x), static_cast<T *>(a.y));
@@ -764,6 +766,8 @@ static hipError_t launch_apply_v(const ApplyLaunch &a)
     } else {
         const int64_t nblk = (int64_t)a.v.ney * a.v.nez * ((a.v.nex + G - 1) / G);
         auto kern = k_apply<P, Q, COLLOC, MODE, VARK, T, G, NT, VC, OTF>;
+        const hipError_t e = prepare_lds(kern, lds);
+        if (e != hipSuccess) return e;
         hipLaunchKernelGGL(kern, dim3((unsigned)nblk), dim3(NT), lds, a.stream, static_cast<const T *>(a.basis_dev),
                            a.v.nex, a.v.ney, a.nvec, a.v.offsets, static_cast<const T *>(a.v.qdata), a.v.kappa,
                            a.wdet, a.vert, static_cast<const T *>(a.x), static_cast<T *>(a.y));

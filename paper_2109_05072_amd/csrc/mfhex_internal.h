@@ -151,7 +151,10 @@ constexpr size_t apply_lds(int Q, int mode, int elem_bytes, int v, bool otf = fa
                elem_bytes +
            (otf ? (size_t)otf_lds_doubles(Q, variant_g(Q, v, mode)) * 8 : 0);
 }
-constexpr size_t kMaxLds = 65536;
+// Largest dynamic LDS of one thread group (gfx950 has 160 KB per CU; above 64 KB the kernel is
+// launched with a raised limit).  96 KB admits 8-vector chunks at q = 7, 4-vector chunks at q = 9
+// and 16-vector chunks at q = 6 while still leaving room for a second group on the CU.
+constexpr size_t kMaxLds = 98304;
 
 // Single-vector launch defaults per q (index q-2): the variant and, for the
 // mass operator, the pipeline depth measured fastest (median of interleaved
