@@ -431,6 +431,14 @@ k_apply(const T *__restrict__ bas, const int nex, const int ney, const int nvec,
         }
     }
 
+    // Chunks of several vectors: the input values of the first chunk are loaded here and each later
+    // chunk's right after the previous chunk is in LDS, so their memory latency overlaps that
+    // chunk's contractions.  (One-vector groups keep no such registers: at q = 10 they would cost
+    // a wavefront per SIMD.)
+    constexpr bool PREFETCH = VC > 1 && MODE != kRhs && !OTF;
+    T xn[PREFETCH ? NodeIO<P, G, NT, VC>::NR : 1];
+    if constexpr (PREFETCH) gather_load<P, G, NT, VC>(xn, off, x, nvec, 0, tid);
+
     for (int v0 = 0; v0 < nvec; v0 += VC) {
         if constexpr (MODE == kRhs) {
             static_assert(VC == 1, "load vector: one vector");
@@ -470,6 +478,9 @@ k_apply(const T *__restrict__ bas, const int nex, const int ney, const int nvec,
                     }
                 }
                 gather_store<P, Q, G, NT, VC>(SPLIT && COLLOC ? s3 : s0, xv, off, nvec, v0, nvalid, tid);
+            } else if constexpr (PREFETCH) {
+                gather_store<P, Q, G, NT, VC>(s0, xn, off, nvec, v0, nvalid, tid);
+                if (v0 + VC < nvec) gather_load<P, G, NT, VC>(xn, off, x, nvec, v0 + VC, tid);
             } else {
                 gather<P, Q, G, NT, VC, T>(SPLIT && COLLOC ? s3 : s0, off, x, nvec, v0, nvalid, tid);
             }
