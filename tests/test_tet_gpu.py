@@ -136,3 +136,23 @@ def test_tet_rejects_aliasing_and_bad_sizes(gpu_lib):
     with pytest.raises(L.MFHexError) as ei:
         gpu_lib.TetOperator(2, 2, 2, 7, synth.mesh_vertices(2, 2, 2))
     assert ei.value.code == L.MFHEX_ERR_UNSUPPORTED
+
+
+def test_tet_degenerate_element_is_reported(gpu_lib):
+    # two neighbouring interior vertices moved onto each other: every tetrahedron holding the edge
+    # between them has two equal corners, det J = 0
+    from paper_2109_05072_amd import _lib as L
+    vert = synth.mesh_vertices(4, 3, 3)
+    v = lambda i, j, k: i + 5 * (j + 4 * k)
+    vert[v(2, 1, 1)] = vert[v(1, 1, 1)]
+    with pytest.raises(L.MFHexError) as ei:
+        gpu_lib.TetOperator(4, 3, 3, 2, vert)
+    assert ei.value.code == L.MFHEX_ERR_MESH
+
+
+def test_tet_fully_masked_mesh_gives_zero(gpu_lib):
+    # one cube, p = 1: all 8 nodes lie on the box boundary
+    op, pr = build(gpu_lib, (1, 1, 1), 1)
+    assert op.n_elem == 6 and op.n_nodes == 8
+    y = host(op.apply(dev(synth.uniform_vector(8)), dev(np.full(8, 3.0))))
+    assert np.all(y == 0.0)
