@@ -97,10 +97,11 @@ void gauss_jacobi_01(int n, int alpha, double *s, double *w)
 {
     const double A = alpha;
     std::vector<double> a(n), b(n, 0.0), x(n);
+    // Jacobi matrix of P^(A,0): diagonal -A^2 / (t (t+2)) with t = 2k + A (first row -A / (A+2)),
+    // off-diagonal sqrt(4 k^2 (k+A)^2 / (t^2 (t+1)(t-1)))
     for (int k = 0; k < n; ++k) {
         const double t = 2.0 * k + A;
-        a[k] = (k == 0 && t + 2.0 == 0.0) ? 0.0 : (0.0 - A * A) / (t * (t + 2.0));
-        if (k == 0) a[k] = -A / (A + 2.0);
+        a[k] = k == 0 ? -A / (A + 2.0) : -A * A / (t * (t + 2.0));
         if (k >= 1) {
             const double kk = k;
             b[k] = std::sqrt(4.0 * kk * (kk + A) * kk * (kk + A) / (t * t * (t + 1.0) * (t - 1.0)));
