@@ -430,9 +430,13 @@ def tet_bench(orders=(2, 3, 4, 5, 6), dofs=1e7, reps=20):
         P, Q, Qp, Pk, Pn = tet_dims(p, op.q)
         E, N = op.n_elem, op.n_nodes
         useful = E * (12.0 * Q * P + 15.0 * Q)          # two products of 3Q x P per element + the 3x3 per point
-        groups = -(-E // 16)
+        # p <= 3: the library groups the 12 tetrahedra of two hexahedra per wavefront and computes their
+        # restriction from the block coordinates (no offset array); otherwise 16 elements per
+        # wavefront with a stored int32 restriction
+        pairs = p <= 3
+        groups = ((ne + 1) // 2) * ne * ne if pairs else -(-E // 16)
         issued = groups * 2048.0 * (3 * (Qp // 16) * (Pk // 4) + 12 * (Qp // 16) * (Pn // 16))
-        byts = 8 * N + 8 * N + 4 * E * P + 48 * E * Q
+        byts = 8 * N + 8 * N + (0 if pairs else 4 * E * P) + 48 * E * Q
         t = ms / 1e3
         r = {"p": p, "q": op.q, "elements": E, "dofs": N, "basis_per_elem": P, "points_per_elem": Q, "ms": round(ms, 4),
              "gdofs": round(N / t / 1e9, 3), "useful_tflops": round(useful / t / 1e12, 2),

@@ -38,6 +38,7 @@ struct mfhex_tet_s {
     int64_t E = 0, ngroups = 0, N = 0;
     double *afrag = nullptr, *bfrag = nullptr, *qdata = nullptr;
     int32_t *offsets = nullptr;
+    const int32_t *lattice = nullptr;
 };
 
 namespace mfhex {
@@ -211,11 +212,18 @@ Layout layout(const mfhex_tet_desc &d, const Dims &D, int64_t ngroups)
     L.bad = o;
     o += 256;
     L.offsets = o;
-    o += al((size_t)ngroups * D.P * kGroup * 4);
+    if (!pair_groups(D.p)) o += al((size_t)ngroups * D.P * kGroup * 4);
     L.qdata = o;
     o += al((size_t)ngroups * D.Q * 6 * kGroup * 8);
     L.total = o;
     return L;
+}
+
+// Element groups: 16 consecutive elements, or (low orders) the two x-adjacent hexahedra of a pair.
+int64_t n_groups(const mfhex_tet_desc &d)
+{
+    if (pair_groups(d.p)) return (int64_t)((d.nex + 1) / 2) * d.ney * d.nez;
+    return (6LL * d.nex * d.ney * d.nez + kGroup - 1) / kGroup;
 }
 
 int validate(const mfhex_tet_desc *d)
@@ -248,7 +256,7 @@ int mfhex_tet_query(const mfhex_tet_desc *d, mfhex_tet_sizes *out)
     if (c) return c;
     if (!out) return fail_global(MFHEX_ERR_ARG, "null output");
     const Dims D = dims(d->p, d->q);
-    const int64_t E = 6LL * d->nex * d->ney * d->nez, G = (E + kGroup - 1) / kGroup;
+    const int64_t E = 6LL * d->nex * d->ney * d->nez, G = n_groups(*d);
     out->n_nodes = (int64_t)(d->p * (int64_t)d->nex + 1) * (d->p * (int64_t)d->ney + 1) * (d->p * (int64_t)d->nez + 1);
     out->n_elem = E;
     out->n_qpts = E * D.Q;
@@ -289,7 +297,7 @@ int mfhex_tet_create(const mfhex_tet_desc *d, void *workspace_dev, size_t worksp
     op->D = dims(d->p, d->q);
     op->E = sz.n_elem;
     op->N = sz.n_nodes;
-    op->ngroups = (op->E + kGroup - 1) / kGroup;
+    op->ngroups = n_groups(*d);
     const Dims &D = op->D;
     const tet::Layout L = layout(*d, D, op->ngroups);
     char *w = static_cast<char *>(workspace_dev);
@@ -316,7 +324,8 @@ int mfhex_tet_create(const mfhex_tet_desc *d, void *workspace_dev, size_t worksp
     const size_t nv = (size_t)(d->nex + 1) * (d->ney + 1) * (d->nez + 1) * 3;
     op->afrag = reinterpret_cast<double *>(w + L.afrag);
     op->bfrag = reinterpret_cast<double *>(w + L.bfrag);
-    op->offsets = reinterpret_cast<int32_t *>(w + L.offsets);
+    op->offsets = pair_groups(d->p) ? nullptr : reinterpret_cast<int32_t *>(w + L.offsets);
+    op->lattice = reinterpret_cast<const int32_t *>(w + L.lattice);
     op->qdata = reinterpret_cast<double *>(w + L.qdata);
     int *bad = reinterpret_cast<int *>(w + L.bad);
     if ((c = check_hip(nullptr, hipMemcpyAsync(op->afrag, af.data(), af.size() * 8, hipMemcpyHostToDevice, s), "copy")) ||
@@ -364,6 +373,11 @@ int mfhex_tet_apply(mfhex_tet op, const double *x_dev, double *y_dev, void *stre
     TetLaunch a{};
     a.p = op->D.p;
     a.q = op->D.q;
+    a.nex = op->d.nex;
+    a.ney = op->d.ney;
+    a.nez = op->d.nez;
+    a.dirichlet = op->d.dirichlet;
+    a.lattice = op->lattice;
     a.nelem = op->E;
     a.ngroups = op->ngroups;
     a.afrag = op->afrag;

@@ -16,6 +16,13 @@ constexpr int kMaxP = 6;
 constexpr int kGroup = 16;       // elements per wavefront (the N extent of one matrix-core tile)
 constexpr int kWaves = 4;        // wavefronts per thread group
 constexpr int n_basis(int p) { return (p + 1) * (p + 2) * (p + 3) / 6; }
+// Low orders group elements by pairs of x-adjacent hexahedra (their 12 tetrahedra in columns 0..11
+// of the wavefront's 16): the pair's element results are summed on chip over its
+// (2p+1) x (p+1) x (p+1) lattice block before one global atomic per block node, and the
+// restriction is computed from the block coordinates instead of read.  (At p = 2 each lattice node
+// is shared by about 7 tetrahedra; per-element atomics dominate there.)
+constexpr bool pair_groups(int p) { return p <= 3; }
+constexpr int pair_block_nodes(int p) { return (2 * p + 1) * (p + 1) * (p + 1); }
 constexpr int round_up(int n, int m) { return (n + m - 1) / m * m; }
 
 // Sizes of one (p, q) instance: P basis functions, Q = q^3 points, padded to
@@ -41,9 +48,11 @@ constexpr size_t bfrag_len(const Dims &D) { return (size_t)(D.Qp / 16) * 3 * 4 *
 
 struct TetLaunch {
     int p, q;
+    int nex, ney, nez, dirichlet;   // pair groups: the mesh, for the computed restriction
     int64_t nelem, ngroups;
+    const int32_t *lattice;         // [P][4]: n1, n2, n3 of each basis function's node
     const double *afrag, *bfrag;
-    const int32_t *offsets;  // [ngroups][P][16], -1 = masked node or no element
+    const int32_t *offsets;  // [ngroups][P][16], -1 = masked node or no element (not with pair groups)
     const double *qdata;     // [ngroups][Q][6][16]: w |det J| J^-1 J^-T (xx, yy, zz, yz, xz, xy)
     const double *x;
     double *y;

@@ -81,16 +81,32 @@ __global__ void k_tet_offsets(int p, int P, int nex, int ney, int nez, int diric
 }
 
 // qdata[g][m][6][16] = w_m |det J| J^-1 J^-T = w_m adj(J) adj(J)^T / |det J| (xx, yy, zz, yz, xz, xy).
-__global__ void k_tet_qdata(int Q, int nex, int ney, int64_t nelem, int64_t nslots, const double *__restrict__ vert,
-                            const double *__restrict__ wq, double *__restrict__ qdata, int *__restrict__ bad)
+// Element of column j of group g (-1: empty column).
+__device__ __forceinline__ int64_t group_element(int64_t g, int j, bool pairs, int nex, int ney, int64_t nelem)
+{
+    if (!pairs) {
+        const int64_t e = g * kGroup + j;
+        return e < nelem ? e : -1;
+    }
+    const int npx = (nex + 1) / 2;
+    const int px = (int)(g % npx);
+    const int64_t row = g / npx;  // ey + ney ez
+    const int cx = 2 * px + j / 6;
+    if (j >= 12 || cx >= nex) return -1;
+    return 6 * (cx + (int64_t)nex * row) + j % 6;
+}
+
+__global__ void k_tet_qdata(int Q, int nex, int ney, int pairs, int64_t nelem, int64_t nslots,
+                            const double *__restrict__ vert, const double *__restrict__ wq, double *__restrict__ qdata,
+                            int *__restrict__ bad)
 {
     const int64_t slot = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (slot >= nslots) return;
     const int64_t g = slot / kGroup;
     const int j = (int)(slot % kGroup);
-    const int64_t e = slot;
+    const int64_t e = group_element(g, j, pairs != 0, nex, ney, nelem);
     double M[6] = {0, 0, 0, 0, 0, 0};
-    if (e < nelem) {
+    if (e >= 0) {
         const int64_t cube = e / 6;
         const int t = (int)(e % 6);
         const int ex = (int)(cube % nex), ey = (int)((cube / nex) % ney), ez = (int)(cube / ((int64_t)nex * ney));
@@ -138,31 +154,79 @@ __global__ void k_tet_qdata(int Q, int nex, int ney, int64_t nelem, int64_t nslo
 // LDS: the gradient fragments of one point block, shared by the kWaves element groups of the thread group.
 constexpr size_t frag_block_doubles(const Dims &D) { return (size_t)3 * (D.Pk / 4) * 64 + (size_t)12 * (D.Pn / 16) * 64; }
 
+// Pair groups: lattice-block coordinates (bx, by, bz) in [0, 2p] x [0, p] x [0, p] of basis
+// function n of column j (tetrahedron j % 6 of hexahedron j / 6 of the pair).
+__device__ __forceinline__ void pair_block_coords(int p, int j, const int32_t *__restrict__ lattice, int n, int &bx,
+                                                  int &by, int &bz)
+{
+    int a0, a1, a2;
+    kuhn_perm(j % 6, a0, a1, a2);
+    (void)a2;
+    const int n1 = lattice[4 * n], n2 = lattice[4 * n + 1], n3 = lattice[4 * n + 2];
+    int a[3] = {n3, n3, n3};
+    a[a0] += n1 + n2;
+    a[a1] += n2;
+    bx = (j / 6) * p + a[0];
+    by = a[1];
+    bz = a[2];
+}
+
+// Global lattice node of block node (bx, by, bz) of pair (px, row), -1 if masked or past the mesh.
+__device__ __forceinline__ int32_t pair_node(int p, int nex, int ney, int nez, int dirichlet, int px, int64_t row,
+                                             int bx, int by, int bz)
+{
+    const int nx = p * nex + 1, ny = p * ney + 1, nz = p * nez + 1;
+    const int ey = (int)(row % ney), ez = (int)(row / ney);
+    const int I = 2 * p * px + bx, J = p * ey + by, K = p * ez + bz;
+    if (I >= nx) return -1;
+    if (dirichlet && (I == 0 || I == nx - 1 || J == 0 || J == ny - 1 || K == 0 || K == nz - 1)) return -1;
+    return I + nx * (J + ny * K);
+}
+
 template <int p, int q>
 __global__ void __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(p == 4 ? 3 : 2)))
-k_tet_apply(int64_t ngroups, const double *__restrict__ afrag, const double *__restrict__ bfrag,
-            const int32_t *__restrict__ offsets, const double *__restrict__ qdata, const double *__restrict__ x,
-            double *__restrict__ y)
+k_tet_apply(int64_t ngroups, int nex, int ney, int nez, int dirichlet, const int32_t *__restrict__ lattice,
+            const double *__restrict__ afrag, const double *__restrict__ bfrag, const int32_t *__restrict__ offsets,
+            const double *__restrict__ qdata, const double *__restrict__ x, double *__restrict__ y)
 {
     constexpr Dims D = dims(p, q);
     constexpr int P = D.P, Q = D.Q, NS = D.Pk / 4, NT = D.Pn / 16, NB = D.Qp / 16;
     constexpr int AL = 3 * NS * 64, BL = 12 * NT * 64, FL = AL + BL;
+    constexpr bool PAIRS = pair_groups(p);
+    constexpr int NBLK = pair_block_nodes(p), BXN = 2 * p + 1, BYN = p + 1;
     extern __shared__ __align__(16) double sfrag[];
-    const int lane = threadIdx.x & 63;
-    const int64_t g0 = xcd_remap(blockIdx.x, gridDim.x) * kWaves + threadIdx.x / 64;  // wavefront-uniform
+    const int lane = threadIdx.x & 63, wave = threadIdx.x / 64;
+    const int64_t g0 = xcd_remap(blockIdx.x, gridDim.x) * kWaves + wave;  // wavefront-uniform
     // every wavefront takes part in the staging and its barriers; one past the last group computes on
     // the last group's data and stores nothing
     const bool active = g0 < ngroups;
     const int64_t g = active ? g0 : ngroups - 1;
     const int el = lane % 16, kq = lane / 16;
-    const int32_t *off = offsets + (size_t)g * P * kGroup;
+    const int32_t *off = PAIRS ? nullptr : offsets + (size_t)g * P * kGroup;
+    // pair groups: pair coordinates, whether column el holds an element, this wavefront's block sums
+    const int npx = (nex + 1) / 2;
+    const int px = (int)(g % npx);
+    const int64_t row = g / npx;
+    const bool col_ok = el < 12 && 2 * px + el / 6 < nex;
+    double *const sblk = sfrag + FL + wave * round_up(NBLK, 2);
+    if constexpr (PAIRS)
+        for (int i = lane; i < NBLK; i += 64) sblk[i] = 0.0;
 
     // B operand of phase 1: lane holds X[basis 4s + kq][element el] for every step s
     double xf[NS];
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
         const int n = 4 * s + kq;
-        const int32_t o = n < P ? off[n * kGroup + el] : -1;
+        int32_t o = -1;
+        if constexpr (PAIRS) {
+            if (col_ok && n < P) {
+                int bx, by, bz;
+                pair_block_coords(p, el, lattice, n, bx, by, bz);
+                o = pair_node(p, nex, ney, nez, dirichlet, px, row, bx, by, bz);
+            }
+        } else {
+            o = n < P ? off[n * kGroup + el] : -1;
+        }
         xf[s] = o >= 0 ? x[o] : 0.0;
     }
     d4 yacc[NT];
@@ -237,14 +301,41 @@ k_tet_apply(int64_t ngroups, const double *__restrict__ afrag, const double *__r
     }
     if (!active) return;
     // result register r of tile t: element 4 r + kq, basis function 16 t + el
+    if constexpr (PAIRS) {
+        // sum the pair's 12 element results over its lattice block on chip, then one atomic per node
 #pragma unroll
-    for (int t = 0; t < NT; ++t) {
-        const int n = 16 * t + el;
-        if (n < P) {
+        for (int t = 0; t < NT; ++t) {
+            const int n = 16 * t + el;
+            if (n < P) {
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int32_t o = off[n * kGroup + 4 * r + kq];
-                if (o >= 0) unsafeAtomicAdd(&y[o], yacc[t][r]);
+                for (int r = 0; r < 4; ++r) {
+                    const int j = 4 * r + kq;
+                    if (j < 12 && 2 * px + j / 6 < nex) {
+                        int bx, by, bz;
+                        pair_block_coords(p, j, lattice, n, bx, by, bz);
+                        atomicAdd(&sblk[bx + BXN * (by + BYN * bz)], yacc[t][r]);
+                    }
+                }
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        for (int i = lane; i < NBLK; i += 64) {
+            const int bx = i % BXN, by = (i / BXN) % BYN, bz = i / (BXN * BYN);
+            const int32_t o = pair_node(p, nex, ney, nez, dirichlet, px, row, bx, by, bz);
+            if (o >= 0) unsafeAtomicAdd(&y[o], sblk[i]);
+        }
+    } else {
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            const int n = 16 * t + el;
+            if (n < P) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int32_t o = off[n * kGroup + 4 * r + kq];
+                    if (o >= 0) unsafeAtomicAdd(&y[o], yacc[t][r]);
+                }
             }
         }
     }
@@ -254,15 +345,16 @@ template <int p, int q>
 hipError_t apply_pq(const TetLaunch &a)
 {
     const int64_t nblk = (a.ngroups + kWaves - 1) / kWaves;
-    const size_t lds = frag_block_doubles(dims(p, q)) * sizeof(double);
+    const size_t lds = (frag_block_doubles(dims(p, q)) + (pair_groups(p) ? kWaves * round_up(pair_block_nodes(p), 2) : 0)) *
+                       sizeof(double);
     auto kern = k_tet_apply<p, q>;
     if (lds > 65536) {
         const hipError_t e =
             hipFuncSetAttribute(reinterpret_cast<const void *>(kern), hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(kern, dim3((unsigned)nblk), dim3(64 * kWaves), lds, a.stream, a.ngroups, a.afrag, a.bfrag,
-                       a.offsets, a.qdata, a.x, a.y);
+    hipLaunchKernelGGL(kern, dim3((unsigned)nblk), dim3(64 * kWaves), lds, a.stream, a.ngroups, a.nex, a.ney, a.nez,
+                       a.dirichlet, a.lattice, a.afrag, a.bfrag, a.offsets, a.qdata, a.x, a.y);
     return hipGetLastError();
 }
 
@@ -279,13 +371,16 @@ hipError_t apply_p(const TetLaunch &a)
 hipError_t launch_tet_setup(const TetSetupLaunch &s)
 {
     const int P = n_basis(s.p), Q = s.q * s.q * s.q;
+    const bool pairs = pair_groups(s.p);
     const int64_t total = s.ngroups * P * kGroup, nslots = s.ngroups * kGroup;
-    hipLaunchKernelGGL(k_tet_offsets, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s.stream, s.p, P, s.nex,
-                       s.ney, s.nez, s.dirichlet, s.nelem, total, s.lattice, s.offsets);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    if (!pairs) {
+        hipLaunchKernelGGL(k_tet_offsets, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s.stream, s.p, P, s.nex,
+                           s.ney, s.nez, s.dirichlet, s.nelem, total, s.lattice, s.offsets);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
     hipLaunchKernelGGL(k_tet_qdata, dim3((unsigned)((nslots + 127) / 128)), dim3(128), 0, s.stream, Q, s.nex, s.ney,
-                       s.nelem, nslots, s.vert, s.wq, s.qdata, s.bad);
+                       pairs ? 1 : 0, s.nelem, nslots, s.vert, s.wq, s.qdata, s.bad);
     return hipGetLastError();
 }
 
