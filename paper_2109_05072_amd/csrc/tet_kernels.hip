@@ -213,21 +213,27 @@ k_tet_apply(int64_t ngroups, int nex, int ney, int nez, int dirichlet, const int
         for (int i = lane; i < NBLK; i += 64) sblk[i] = 0.0;
 
     // B operand of phase 1: lane holds X[basis 4s + kq][element el] for every step s
+    // (branch-free: every load is issued, from a clamped index, and the value selected afterwards, so
+    // the loads of all steps are in flight together instead of one round trip per step)
     double xf[NS];
+    int32_t xo[NS];
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
         const int n = 4 * s + kq;
-        int32_t o = -1;
         if constexpr (PAIRS) {
-            if (col_ok && n < P) {
-                int bx, by, bz;
-                pair_block_coords(p, el, lattice, n, bx, by, bz);
-                o = pair_node(p, nex, ney, nez, dirichlet, px, row, bx, by, bz);
-            }
+            int bx, by, bz;
+            pair_block_coords(p, el, lattice, n < P ? n : P - 1, bx, by, bz);
+            const int32_t o = pair_node(p, nex, ney, nez, dirichlet, px, row, bx, by, bz);
+            xo[s] = col_ok && n < P ? o : -1;
         } else {
-            o = n < P ? off[n * kGroup + el] : -1;
+            const int32_t o = off[(n < P ? n : P - 1) * kGroup + el];
+            xo[s] = n < P ? o : -1;
         }
-        xf[s] = o >= 0 ? x[o] : 0.0;
+    }
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        const double v = x[xo[s] >= 0 ? xo[s] : 0];
+        xf[s] = xo[s] >= 0 ? v : 0.0;
     }
     d4 yacc[NT];
 #pragma unroll
@@ -252,7 +258,10 @@ k_tet_apply(int64_t ngroups, int nex, int ney, int nez, int dirichlet, const int
             const int m = 16 * b + 4 * r + kq;
             const double *qd = qg + (size_t)(m < Q ? m : Q - 1) * 6 * kGroup;
 #pragma unroll
-            for (int f = 0; f < 6; ++f) qv[r][f] = m < Q ? qd[f * kGroup] : 0.0;
+            for (int f = 0; f < 6; ++f) {
+                const double v = qd[f * kGroup];
+                qv[r][f] = m < Q ? v : 0.0;
+            }
         }
         {
             const double *bb = bfrag + (size_t)b * BL;
