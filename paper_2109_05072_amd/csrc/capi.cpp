@@ -164,7 +164,9 @@ int default_variant(const mfhex_op_s &op, int prec, int nvec)
     // several: the largest chunk that fits the LDS budget and does not exceed
     // the vector count
     if (nvec <= 1) {
-        const int v = (mode_of(op) == kMass ? kDefVariantMass : kDefVariantDiff)[op.Q - 2];
+        const int v = (mode_of(op) == kMass            ? kDefVariantMass
+                       : prec == MFHEX_F32 ? kDefVariantDiff32
+                                           : kDefVariantDiff)[op.Q - 2];
         return valid_variant(op, prec, v) ? v : 0;
     }
     for (int v = kNumVariants - 1; v >= 5; --v)

@@ -161,6 +161,11 @@ constexpr size_t kMaxLds = 98304;
 // timings at about 1e7 DOFs on perturbed box meshes, Gauss q = p+2); orders
 // not measured there keep variant 0.
 constexpr int kDefVariantDiff[9] = {0, 0, 0, 4, 3, 0, 0, 1, 0};
+// FP32 diffusion (the operator inside mixed-precision CG): half the register and LDS footprint
+// favours two-element groups at q = 7 and 8 (5-13% and 20-27% faster than the FP64 choice at 1e7
+// and 3e7 nodes); at q = 9 the best choice changes with the mesh size, and it and the other q
+// keep the FP64 choice.
+constexpr int kDefVariantDiff32[9] = {0, 0, 0, 4, 3, 1, 3, 1, 0};
 constexpr int kDefVariantMass[9] = {0, 0, 0, 3, 3, 1, 3, 0, 4};
 constexpr int kDefChainMass[9] = {2, 2, 2, 4, 2, 4, 4, 4, 2};
 // Device basis block (elements): B [Q][P], B^T [P][Q], D [Q][Q], D^T [Q][Q],
