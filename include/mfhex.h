@@ -136,7 +136,8 @@ int mfhex_apply_adjoint(mfhex_op op, int prec, int nrhs, const void *x_dev, void
 /* Gradient of s = r^T (M A(kappa) M) u with respect to the per-point
  * coefficient: g[e][pt] = (Dhat M r)_pt^T G0_pt (Dhat M u)_pt, G0 the
  * kappa-free geometric factors.  u, r: device FP64 [n_nodes] (ncomp = 1);
- * g: device FP64 [n_elem][q^3], overwritten.  Diffusion operators only.
+ * g: device FP64 [n_elem][q^3], overwritten.  Diffusion operators with
+ * stored geometric factors only (MFHEX_ERR_UNSUPPORTED with MFHEX_FLAG_OTF).
  * For a loss L(y), r = dL/dy gives dL/dkappa.  Asynchronous. */
 int mfhex_kappa_grad(mfhex_op op, const double *u_dev, const double *r_dev, double *g_dev, void *stream);
 
@@ -193,8 +194,9 @@ typedef struct {
 
 /* Solve A x = b.  b, x: device FP64 [n_nodes] (ncomp = 1).  cg_work_dev:
  * caller-owned device buffer of sizes.cg_work_bytes.  rhist (may be NULL):
- * HOST array of maxit+1 doubles receiving ||r_k|| (recursive) after each
- * iteration when check_every == 1 or max_iters_exact == 1.  Synchronizes
+ * HOST array of maxit+1 doubles receiving ||r_0|| and then ||r_k||
+ * (recursive) after each iteration; entries past 8191 iterations are not
+ * written.  Synchronizes
  * `stream`.  Returns MFHEX_OK on convergence, MFHEX_ERR_NOCONV at maxit,
  * MFHEX_ERR_BREAKDOWN on p^T A p <= 0 / non-finite values.  (Sec. 1: CG
  * on the sum-factorized operator; Sec. 2: the benchmarks run it
@@ -328,8 +330,9 @@ int mfhex_tet_query(const mfhex_tet_desc *d, mfhex_tet_sizes *out);
 int mfhex_tet_create(const mfhex_tet_desc *d, void *workspace_dev, size_t workspace_bytes, void *stream,
                      mfhex_tet *out);
 
-/* y = A x, FP64 device vectors [n_nodes], distinct.  Asynchronous on `stream`
- * (y is zeroed first, then summed with atomics). */
+/* y = A x, FP64 device vectors [n_nodes] that must not overlap (else
+ * MFHEX_ERR_ARG).  Asynchronous on `stream` (y is zeroed first, then summed
+ * with atomics). */
 int mfhex_tet_apply(mfhex_tet op, const double *x_dev, double *y_dev, void *stream);
 
 int mfhex_tet_destroy(mfhex_tet op);

@@ -370,6 +370,8 @@ int mfhex_create(const mfhex_desc *d, void *workspace_dev, size_t workspace_byte
     op->basis32 = reinterpret_cast<float *>(ws + L.basis + ((basis_len(op->P, op->Q) * sizeof(double) + 255) & ~size_t(255)));
     hipStream_t s = static_cast<hipStream_t>(stream);
     auto bail = [&](int code) {
+        // queued copies read host memory that the caller may free after the return
+        (void)hipStreamSynchronize(s);
         g_err = op->err;
         if (op->pinned) (void)hipHostFree(op->pinned);
         delete op;
@@ -488,6 +490,7 @@ int mfhex_kappa_grad(mfhex_op op, const double *u_dev, const double *r_dev, doub
     if (!op) return fail(MFHEX_ERR_ARG, "null handle");
     if (op->d.kind != MFHEX_DIFFUSION) return set_error(op, MFHEX_ERR_STATE, "coefficient gradient needs a diffusion operator");
     if (op->d.ncomp != 1) return set_error(op, MFHEX_ERR_UNSUPPORTED, "coefficient gradient needs ncomp = 1");
+    if (!op->q64) return set_error(op, MFHEX_ERR_UNSUPPORTED, "coefficient gradient needs stored geometric factors");
     if (!u_dev || !r_dev || !g_dev) return set_error(op, MFHEX_ERR_ARG, "null vector");
     KgradLaunch a{};
     a.v = view_of(*op, MFHEX_F64);

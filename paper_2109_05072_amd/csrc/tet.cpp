@@ -302,6 +302,11 @@ int mfhex_tet_create(const mfhex_tet_desc *d, void *workspace_dev, size_t worksp
     const tet::Layout L = layout(*d, D, op->ngroups);
     char *w = static_cast<char *>(workspace_dev);
     hipStream_t s = static_cast<hipStream_t>(stream);
+    // on a failure after copies were queued, wait for them: their host sources are locals
+    auto drain = [&](int code) {
+        (void)hipStreamSynchronize(s);
+        return code;
+    };
 
     // gradient matrices G_d [Q][P] at the rule's points, as matrix-core fragments
     const Rule R = tet_rule(d->q);
@@ -335,7 +340,7 @@ int mfhex_tet_create(const mfhex_tet_desc *d, void *workspace_dev, size_t worksp
         (c = check_hip(nullptr, hipMemcpyAsync(w + L.wq, R.w.data(), R.w.size() * 8, hipMemcpyHostToDevice, s), "copy")) ||
         (c = check_hip(nullptr, hipMemcpyAsync(w + L.vert, d->vertex_xyz, nv * 8, hipMemcpyHostToDevice, s), "copy")) ||
         (c = check_hip(nullptr, hipMemsetAsync(bad, 0, sizeof(int), s), "hipMemsetAsync")))
-        return c;
+        return drain(c);
     TetSetupLaunch S{};
     S.p = d->p;
     S.q = d->q;
@@ -352,7 +357,7 @@ int mfhex_tet_create(const mfhex_tet_desc *d, void *workspace_dev, size_t worksp
     S.qdata = op->qdata;
     S.bad = bad;
     S.stream = s;
-    if ((c = check_hip(nullptr, launch_tet_setup(S), "tetrahedral set-up kernel"))) return c;
+    if ((c = check_hip(nullptr, launch_tet_setup(S), "tetrahedral set-up kernel"))) return drain(c);
     int hbad = 0;
     if ((c = check_hip(nullptr, hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, s), "copy")) ||
         (c = check_hip(nullptr, hipStreamSynchronize(s), "hipStreamSynchronize")))
@@ -366,7 +371,8 @@ int mfhex_tet_apply(mfhex_tet op, const double *x_dev, double *y_dev, void *stre
 {
     if (!op) return fail_global(MFHEX_ERR_ARG, "null handle");
     if (!x_dev || !y_dev) return fail_global(MFHEX_ERR_ARG, "null vector");
-    if (x_dev == y_dev) return fail_global(MFHEX_ERR_ARG, "x and y alias");
+    const uintptr_t xa = (uintptr_t)x_dev, ya = (uintptr_t)y_dev, bytes = (uintptr_t)op->N * sizeof(double);
+    if (xa < ya + bytes && ya < xa + bytes) return fail_global(MFHEX_ERR_ARG, "x and y overlap");
     hipStream_t s = static_cast<hipStream_t>(stream);
     int c = check_hip(nullptr, hipMemsetAsync(y_dev, 0, (size_t)op->N * sizeof(double), s), "hipMemsetAsync");
     if (c) return c;

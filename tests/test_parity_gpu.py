@@ -400,6 +400,10 @@ def test_otf_workspace_has_no_factor_array_and_rejects_what_needs_one(gpu_lib):
     with pytest.raises(L.MFHexError) as ei:
         op.diagonal()
     assert ei.value.code == L.MFHEX_ERR_UNSUPPORTED
+    u = dev(synth.uniform_vector(pr.n_nodes, seed=4))
+    with pytest.raises(L.MFHexError) as ei:
+        op.kappa_grad(u, u)
+    assert ei.value.code == L.MFHEX_ERR_UNSUPPORTED
     for kw in (dict(kind="mass", dirichlet=False), dict(vark=True), dict(f32=True)):
         with pytest.raises(L.MFHexError) as ei:
             build(gpu_lib, 2, 2, 2, 2, otf=True, **kw)

@@ -131,6 +131,12 @@ def test_tet_rejects_aliasing_and_bad_sizes(gpu_lib):
     with pytest.raises(L.MFHexError) as ei:
         L.mfhex_tet_apply(op.handle, x.data_ptr(), x.data_ptr(), torch.cuda.current_stream().cuda_stream)
     assert ei.value.code == L.MFHEX_ERR_ARG
+    # partial overlap: y starts inside x
+    big = dev(np.zeros(2 * pr.n_nodes))
+    with pytest.raises(L.MFHexError) as ei:
+        L.mfhex_tet_apply(op.handle, big.data_ptr(), big.data_ptr() + 8 * (pr.n_nodes - 1),
+                          torch.cuda.current_stream().cuda_stream)
+    assert ei.value.code == L.MFHEX_ERR_ARG
     with pytest.raises(ValueError):
         op.apply(x[:-1].contiguous())
     with pytest.raises(L.MFHexError) as ei:
