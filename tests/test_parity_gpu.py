@@ -639,7 +639,8 @@ def test_error_paths(gpu_lib):
 # --- full-size, sampled against the oracle one output at a time -----------------------------
 
 def _window_value(vert_full, nex, ney, nez, p, quad, kind, dirichlet, x_full, node):
-    """(A x)[node] from the oracle on the <= 2x2x2 elements around the node."""
+    """(A x)[node] from the oracle on the <= 2x2x2 elements around the node.  x_full: the host
+    vector ([N] or [N][nvec]), or a function returning its rows at given node numbers."""
     nx, ny = p * nex + 1, p * ney + 1
     I, J, K = node % nx, (node // nx) % ny, node // (nx * ny)
     lo, hi = [], []
@@ -658,7 +659,7 @@ def _window_value(vert_full, nex, ney, nez, p, quad, kind, dirichlet, x_full, no
     gj = np.arange(lny)[None, :, None] + p * lo[1]
     gk = np.arange(lnz)[:, None, None] + p * lo[2]
     gid = (gi + nx * (gj + ny * gk)).reshape(-1)
-    xw = x_full[gid].copy()
+    xw = x_full(gid) if callable(x_full) else x_full[gid].copy()
     if dirichlet:
         Gi, Gj, Gk = gid % nx, (gid // nx) % ny, gid // (nx * ny)
         bnd = (Gi == 0) | (Gi == nx - 1) | (Gj == 0) | (Gj == ny - 1) | (Gk == 0) | (Gk == p * nez)
@@ -700,3 +701,48 @@ def test_full_size_sampled_against_oracle(gpu_lib, p, kind):
             continue
         yo = _window_value(vert, ne, ne, ne, p, oracle.GAUSS, kd, dirichlet, x, node)
         assert abs(y[node] - yo) <= TOL64 * scale, (node, y[node], yo)
+
+
+@pytest.mark.parametrize("p,ncomp,nrhs", [(3, 3, 32), (5, 1, 8), (8, 3, 4)])
+def test_batched_full_size_sampled_against_oracle(gpu_lib, p, ncomp, nrhs):
+    """Collocated BP5 / BP6 at the batched benchmark's size (about 3e7 nodes per field), the default
+    launch and every multi-vector variant (the candidates of the tuner), sampled node by node with
+    all vectors of each sampled node."""
+    ne = synth.elems_for_dofs(3e7, p)
+    nvec = ncomp * nrhs
+    _say("batched full size", p, ncomp, nrhs, ne)
+    op, _ = build(gpu_lib, ne, ne, ne, p, "diffusion", "gll", True, ncomp=ncomp)
+    vert = synth.mesh_vertices(ne, ne, ne)
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(synth.SEED_VEC)
+    x = torch.rand(op.n_nodes, nvec, generator=gen, dtype=torch.float64, device="cuda").mul_(2).sub_(1)
+    y = torch.empty_like(x)
+    n = p * ne + 1
+    rng = np.random.default_rng(23)
+    nodes = [int(v) for v in rng.integers(0, op.n_nodes, size=12)]
+    nodes += [1 + n + n * n, (n - 2) + n * (n - 2) + n * n * (n - 2)]
+    nodes += [m * p + n * (2 * p + 1 + n * (2 * p + 1)) for m in range(1, 6)]  # x-faces inside and between groups
+    on_bnd = np.array([min(v % n, v // n % n, v // (n * n)) == 0 or max(v % n, v // n % n, v // (n * n)) == n - 1
+                       for v in nodes])
+    rows = lambda gid: x[torch.from_numpy(gid).to("cuda")].cpu().numpy()
+    # Dirichlet rows are exactly zero; the others come from the oracle on the elements around the node
+    ref = np.stack([np.zeros(nvec) if b else
+                    _window_value(vert, ne, ne, ne, p, oracle.GLL, oracle.DIFFUSION, True, rows, v)
+                    for v, b in zip(nodes, on_bnd)])
+    idx = torch.tensor(nodes, device="cuda")
+
+    def check(tag):
+        op.apply(x, y)
+        ys = host(y[idx])
+        assert np.all(ys[on_bnd] == 0.0), tag
+        scale = y.abs().max().item()
+        err = np.abs(ys - ref).max() / scale
+        print("batched sampled rel err", p, ncomp, nrhs, tag, err)
+        assert err <= TOL64, tag
+
+    _say("launch", op.get_config(nrhs=nrhs))
+    check("default")
+    for v in [v for v in valid_variants(op, nrhs=nrhs) if v >= 5]:
+        op.set_config(v, nrhs=nrhs)
+        _say("launch", op.get_config(nrhs=nrhs))
+        check(v)
