@@ -746,3 +746,66 @@ def test_batched_full_size_sampled_against_oracle(gpu_lib, p, ncomp, nrhs):
         op.set_config(v, nrhs=nrhs)
         _say("launch", op.get_config(nrhs=nrhs))
         check(v)
+
+
+def test_kappa_gradient_full_size(gpu_lib):
+    """The adjoint workload at its size (p = 4, Gauss q = 6, about 1e7 nodes): the coefficient
+    gradient sampled element by element against the oracle on that element alone (inputs masked
+    as in the full operator), and the loss 0.5 ||A(kappa) u - f||^2 differentiated along random
+    directions by central differences (exact for a loss quadratic in kappa and in u)."""
+    from paper_2109_05072_amd.autograd import diffusion
+    p = 4
+    ne = synth.elems_for_dofs(1e7, p)
+    _say("kappa gradient full size", p, ne)
+    op, _ = build(gpu_lib, ne, ne, ne, p, "diffusion", "gauss", True, vark=True)
+    vert = synth.mesh_vertices(ne, ne, ne)
+    n = p * ne + 1
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(synth.SEED_VEC)
+    u = torch.rand(op.n_nodes, generator=gen, dtype=torch.float64, device="cuda").mul_(2).sub_(1)
+    r = torch.rand(op.n_nodes, generator=gen, dtype=torch.float64, device="cuda").mul_(2).sub_(1)
+    g = op.kappa_grad(u, r)
+    scale = g.abs().max().item()
+    rng = np.random.default_rng(29)
+    elems = [int(e) for e in rng.integers(0, op.n_elem, size=16)] + [0, op.n_elem - 1, ne * ne * (ne // 2) + ne // 2]
+    V = vert.reshape(ne + 1, ne + 1, ne + 1, 3)
+    ii = np.arange(p + 1)
+    for e in elems:
+        ex, ey, ez = e % ne, (e // ne) % ne, e // (ne * ne)
+        pr = oracle.Problem(1, 1, 1, p, p + 2, oracle.GAUSS, oracle.DIFFUSION, 0,
+                            np.ascontiguousarray(V[ez:ez + 2, ey:ey + 2, ex:ex + 2].reshape(-1, 3)))
+        I = (p * ex + ii)[None, None, :]
+        J = (p * ey + ii)[None, :, None]
+        K = (p * ez + ii)[:, None, None]
+        gid = (I + n * (J + n * K)).reshape(-1)
+        bnd = ((I == 0) | (I == n - 1) | (J == 0) | (J == n - 1) | (K == 0) | (K == n - 1)).reshape(-1)
+        ids = torch.from_numpy(gid).to("cuda")
+        uw, rw = host(u[ids]), host(r[ids])
+        uw[bnd] = 0.0
+        rw[bnd] = 0.0
+        go = oracle.kappa_grad(pr, uw, rw)[0]
+        err = np.abs(host(g[e]) - go).max() / scale
+        assert err <= TOL64, (e, err)
+    # finite differences of the loss along random directions, in kappa and in u
+    kap = torch.exp(0.5 * torch.rand(op.n_elem, op.q ** 3, generator=gen, dtype=torch.float64, device="cuda"))
+    f = torch.rand(op.n_nodes, generator=gen, dtype=torch.float64, device="cuda")
+    uu = u.clone().requires_grad_(True)
+    k = kap.clone().requires_grad_(True)
+
+    def loss(a, b):
+        res = diffusion(a, b, op) - f
+        return 0.5 * (res * res).sum()
+
+    gu, gk = torch.autograd.grad(loss(uu, k), [uu, k])
+    with torch.no_grad():
+        for _ in range(2):
+            d = torch.randn(kap.shape, generator=gen, dtype=torch.float64, device="cuda")
+            eps = 1e-2 * float(kap.norm() / d.norm())
+            fd = (loss(u, kap + eps * d) - loss(u, kap - eps * d)) / (2 * eps)
+            an = (gk * d).sum()
+            assert abs(float(fd - an)) <= 1e-9 * abs(float(an))
+            du = torch.randn(op.n_nodes, generator=gen, dtype=torch.float64, device="cuda")
+            eps = 1e-2 * float(u.norm() / du.norm())
+            fd = (loss(u + eps * du, kap) - loss(u - eps * du, kap)) / (2 * eps)
+            an = (gu * du).sum()
+            assert abs(float(fd - an)) <= 1e-9 * abs(float(an))
