@@ -227,7 +227,10 @@ __device__ __forceinline__ void load_offsets(int32_t (&off)[NR], const int32_t *
         int g, i;
         line_pos<P, G>(X, nvalid, g, i);
         const int j = line % P, k = line / P;
-        off[r] = (id < IO::NID && line_valid<P, G>(X, nvalid)) ? offsets[(e0 + g) * IO::P3 + i + P * (j + P * k)] : -1;
+        // read once per element: streamed past the caches that keep x and y lines
+        off[r] = (id < IO::NID && line_valid<P, G>(X, nvalid))
+                     ? __builtin_nontemporal_load(&offsets[(e0 + g) * IO::P3 + i + P * (j + P * k)])
+                     : -1;
     }
 }
 
