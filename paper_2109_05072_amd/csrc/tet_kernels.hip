@@ -226,7 +226,7 @@ k_tet_apply(int64_t ngroups, int nex, int ney, int nez, int dirichlet, const int
             const int32_t o = pair_node(p, nex, ney, nez, dirichlet, px, row, bx, by, bz);
             xo[s] = col_ok && n < P ? o : -1;
         } else {
-            const int32_t o = off[(n < P ? n : P - 1) * kGroup + el];
+            const int32_t o = __builtin_nontemporal_load(&off[(n < P ? n : P - 1) * kGroup + el]);
             xo[s] = n < P ? o : -1;
         }
     }
@@ -259,7 +259,7 @@ k_tet_apply(int64_t ngroups, int nex, int ney, int nez, int dirichlet, const int
             const double *qd = qg + (size_t)(m < Q ? m : Q - 1) * 6 * kGroup;
 #pragma unroll
             for (int f = 0; f < 6; ++f) {
-                const double v = qd[f * kGroup];
+                const double v = __builtin_nontemporal_load(&qd[f * kGroup]);
                 qv[r][f] = m < Q ? v : 0.0;
             }
         }
