@@ -18,8 +18,12 @@
  *     library never allocates or frees device memory.  Host pointers are
  *     read during the call only.
  *   - `stream` is a hipStream_t passed as void* (NULL = default stream).
- *     apply / apply_adjoint / kappa_grad / rhs / *_coords enqueue work and
- *     return without synchronizing.  create, cg and tune synchronize it.
+ *     apply / apply_add / apply_adjoint / kappa_grad / diagonal / rhs /
+ *     *_coords / mg_apply / tet_apply enqueue kernels only (outputs are
+ *     cleared by a fill kernel, never by a runtime memset; no allocation and
+ *     no host synchronization), so they may be recorded into a graph by
+ *     stream capture.  create, cg, tune and mg_setup synchronize the stream
+ *     and must not be captured.
  *   - Node numbering: global node (I,J,K), I in [0, p*nex], is
  *     I + (p*nex+1)*(J + (p*ney+1)*K).  Element (ex,ey,ez) is
  *     ex + nex*(ey + ney*ez).  Quadrature point (a,b,c) of an element is

@@ -50,6 +50,8 @@ hipError_t launch_jacobi_inverse(const double *d, double *dinv64, float *dinv32,
 hipError_t launch_residual(const double *b, const double *Ax, double *r64, float *r32, int64_t n, double *partial,
                            hipStream_t s);
 hipError_t launch_copy(const void *src, int ps, void *dst, int pd, int64_t n, hipStream_t s);
+// bytes (a multiple of 4) of zeros at p, by a kernel (graph-capture safe, unlike a runtime memset).
+hipError_t launch_zero(void *p, size_t bytes, hipStream_t s);
 hipError_t launch_fill_uniform(double *x, int64_t n, uint64_t seed, hipStream_t s);
 // out2[0] = max |a - b| (inf if a has a NaN), out2[1] = max |b|; partial holds 2*kRedBlocks doubles.
 hipError_t launch_relmaxdiff(const void *a, const void *b, int64_t n, int prec, double *partial, double *out2,

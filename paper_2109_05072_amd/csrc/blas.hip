@@ -230,6 +230,22 @@ __device__ __forceinline__ uint64_t splitmix64(uint64_t z)
     return z ^ (z >> 31);
 }
 
+// Zero fill as a kernel rather than a runtime memset, so that the asynchronous entry points stay
+// safe to record into a graph.
+// 16-byte stores for the bulk, then the last (bytes mod 16) / 4 words
+__global__ void k_zero16(uint4 *__restrict__ p, int64_t n, uint32_t *__restrict__ tail, int ntail)
+{
+    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    for (int64_t i = t; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = make_uint4(0u, 0u, 0u, 0u);
+    if (t < ntail) tail[t] = 0u;
+}
+
+__global__ void k_zero4(uint32_t *__restrict__ p, int64_t n)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0u;
+}
+
 __global__ void k_fill_uniform(double *__restrict__ x, int64_t n, uint64_t seed)
 {
     for (int64_t i = blockIdx.x * (int64_t)kRedThreads + threadIdx.x; i < n; i += (int64_t)kRedBlocks * kRedThreads) {
@@ -369,6 +385,21 @@ hipError_t launch_copy(const void *src, int ps, void *dst, int pd, int64_t n, hi
         hipLaunchKernelGGL((k_copy<float, double>), GRID, (const float *)src, (double *)dst, n);
     else
         hipLaunchKernelGGL((k_copy<float, float>), GRID, (const float *)src, (float *)dst, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero(void *p, size_t bytes, hipStream_t s)
+{
+    if (bytes % 4) return hipErrorInvalidValue;
+    if (bytes == 0) return hipSuccess;
+    const bool wide = (uintptr_t)p % 16 == 0;
+    const int64_t n = (int64_t)(wide ? bytes / 16 : bytes / 4);
+    const int64_t blocks = n < 256 ? 1 : (n + 255) / 256 < 65536 ? (n + 255) / 256 : 65536;
+    if (wide)
+        hipLaunchKernelGGL(k_zero16, dim3((unsigned)blocks), dim3(256), 0, s, static_cast<uint4 *>(p), n,
+                           reinterpret_cast<uint32_t *>(static_cast<char *>(p) + 16 * n), (int)(bytes % 16 / 4));
+    else
+        hipLaunchKernelGGL(k_zero4, dim3((unsigned)blocks), dim3(256), 0, s, static_cast<uint32_t *>(p), n);
     return hipGetLastError();
 }
 

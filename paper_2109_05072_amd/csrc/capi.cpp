@@ -271,7 +271,7 @@ int apply_impl(mfhex_op op, int prec, int nrhs, const void *x, void *y, hipStrea
     if (nchain > kMaxChain || (nchain > 1 && mode_of(*op) != kMass))
         return set_error(op, MFHEX_ERR_ARG, "invalid pipeline depth");
     if (zero) {
-        const int c = check_hip(op, hipMemsetAsync(y, 0, bytes, s), "hipMemsetAsync");
+        const int c = check_hip(op, launch_zero(y, bytes, s), "zero fill");
         if (c) return c;
     }
     ApplyLaunch a{};
@@ -300,7 +300,7 @@ int diagonal_impl(mfhex_op op, double *d, hipStream_t s)
     if (!d) return set_error(op, MFHEX_ERR_ARG, "null output");
     if (op->d.variable_kappa && !op->kappa_set) return set_error(op, MFHEX_ERR_STATE, "kappa not set");
     if (!op->q64) return set_error(op, MFHEX_ERR_UNSUPPORTED, "the diagonal needs stored geometric factors");
-    int c = check_hip(op, hipMemsetAsync(d, 0, op->N * sizeof(double), s), "hipMemsetAsync");
+    int c = check_hip(op, launch_zero(d, op->N * sizeof(double), s), "zero fill");
     if (c) return c;
     DiagLaunch a{};
     a.v = view_of(*op, MFHEX_F64);
@@ -532,7 +532,7 @@ int mfhex_rhs(mfhex_op op, const double *f_dev, double *b_dev, void *stream)
     const double *wdet = op->d.kind == MFHEX_MASS ? op->q64 : op->wdet;
     if (!wdet) return set_error(op, MFHEX_ERR_STATE, "load vector needs a mass operator or MFHEX_FLAG_RHS");
     hipStream_t s = static_cast<hipStream_t>(stream);
-    int c = check_hip(op, hipMemsetAsync(b_dev, 0, op->N * sizeof(double), s), "hipMemsetAsync");
+    int c = check_hip(op, launch_zero(b_dev, op->N * sizeof(double), s), "zero fill");
     if (c) return c;
     ApplyLaunch a{};
     a.v = view_of(*op, MFHEX_F64);

@@ -240,7 +240,7 @@ int vcycle(mfhex_op fine, MgHierarchy &h, int l, const void *b, void *x, hipStre
     TRY(apply_impl(L.op, h.prec, 1, x, L.ad, s, true, -1));
     TRY(check_hip(fine, launch_mg_residual(b, L.ad, L.r, h.prec, L.n, s), "residual kernel"));
     MgLevel &Cl = h.lv[l + 1];
-    TRY(check_hip(fine, hipMemsetAsync(Cl.b, 0, Cl.n * elem_bytes(h.prec), s), "hipMemsetAsync"));
+    TRY(check_hip(fine, launch_zero(Cl.b, Cl.n * elem_bytes(h.prec), s), "zero fill"));
     TRY(transfer(fine, h, L, Cl, 1, L.r, Cl.b, s));
     TRY(vcycle(fine, h, l + 1, Cl.b, Cl.x, s));
     TRY(transfer(fine, h, L, Cl, 0, Cl.x, x, s));

@@ -29,6 +29,7 @@
 #include <string>
 #include <vector>
 
+#include "blas.h"
 #include "op.h"
 #include "tet.h"
 
@@ -374,7 +375,7 @@ int mfhex_tet_apply(mfhex_tet op, const double *x_dev, double *y_dev, void *stre
     const uintptr_t xa = (uintptr_t)x_dev, ya = (uintptr_t)y_dev, bytes = (uintptr_t)op->N * sizeof(double);
     if (xa < ya + bytes && ya < xa + bytes) return fail_global(MFHEX_ERR_ARG, "x and y overlap");
     hipStream_t s = static_cast<hipStream_t>(stream);
-    int c = check_hip(nullptr, hipMemsetAsync(y_dev, 0, (size_t)op->N * sizeof(double), s), "hipMemsetAsync");
+    int c = check_hip(nullptr, launch_zero(y_dev, (size_t)op->N * sizeof(double), s), "zero fill");
     if (c) return c;
     TetLaunch a{};
     a.p = op->D.p;

@@ -809,3 +809,50 @@ def test_kappa_gradient_full_size(gpu_lib):
             fd = (loss(u + eps * du, kap) - loss(u - eps * du, kap)) / (2 * eps)
             an = (gu * du).sum()
             assert abs(float(fd - an)) <= 1e-9 * abs(float(an))
+
+
+# --- graph capture ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("case", ["bp3-f64", "bp3-f32", "bp6-gll-p8-4rhs", "bp1-mass", "tet-p4"])
+def test_captured_apply_replays_match(gpu_lib, case):
+    """The asynchronous applies only enqueue kernels (the output is cleared by a fill kernel, not a
+    runtime memset), so a caller can record them into a graph.  The graph is replayed several times
+    with eager work and synchronizations between the replays (new input, output set to garbage);
+    every replay must match the oracle and an eager apply of the same input."""
+    from oracle import tet as otet
+    _say("graph", case)
+    if case == "tet-p4":
+        vert = synth.mesh_vertices(3, 3, 2, 0.1)
+        op = gpu_lib.TetOperator(3, 3, 2, 4, vert)
+        pr = otet.TetProblem(3, 3, 2, 4, 4, 1, vert)
+        n, nvec, dt, tol, ref_of = pr.n_nodes, 1, torch.float64, TOL64, (lambda xh: otet.apply(pr, xh))
+    else:
+        # p = 4 on 3 x 3 x 2 elements: 1521 nodes, so the output is not a whole number of 16-byte words
+        kw = {"bp3-f64": dict(p=4), "bp3-f32": dict(p=4, f32=True),
+              "bp6-gll-p8-4rhs": dict(p=8, quad="gll", ncomp=3), "bp1-mass": dict(p=5, kind="mass")}[case]
+        p = kw.pop("p")
+        op, pr = build(gpu_lib, 3, 3, 2, p, **kw)
+        nvec = 12 if case.startswith("bp6") else 1
+        n = pr.n_nodes
+        dt = torch.float32 if case == "bp3-f32" else torch.float64
+        tol = TOL32 if dt == torch.float32 else TOL64
+        ref_of = lambda xh: oracle.apply(pr, xh)
+    shape = (n, nvec) if nvec > 1 else (n,)
+    x = dev(synth.uniform_vector(n, nvec=nvec), dt).reshape(shape).contiguous()
+    y = torch.empty_like(x)
+    op.apply(x, y)  # eager call first: one-time launch set-up happens outside the capture
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        op.apply(x, y)
+    torch.cuda.synchronize()
+    for k in range(4):
+        x.copy_(dev(synth.uniform_vector(n, nvec=nvec, seed=100 + k), dt).reshape(shape))
+        y.fill_(7.0)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        yr = host(y)
+        assert relerr(yr, ref_of(host(x).astype(np.float64))) <= tol, k
+        ye = host(op.apply(x))
+        assert relerr(yr, ye) <= (1e-14 if dt == torch.float64 else 1e-6), k
