@@ -15,7 +15,7 @@ def pytest_configure(config):
 
 @pytest.fixture(scope="session")
 def gpu_lib():
-    """The product binding, loaded only on a GPU machine; fails loudly if the HIP library is missing."""
+    """The product binding, loaded only where a GPU is present; fails loudly if the HIP library is missing."""
     import torch
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
