@@ -151,6 +151,82 @@ __device__ __forceinline__ void contract(const T *src, T *dst, const T *__restri
     }
 }
 
+// Two independent contractions of G cubes Q^3 -> Q^3 with the same folded
+// matrix, along x (src0 -> dst0) and along y (src1 -> dst1), taken as one
+// list of 2 G Q^2 lines: lanes that one contraction would leave idle take
+// lines of the other, and each coefficient row is loaded once for both.  Same
+// lane-to-line order within each contraction as contract(); every line is
+// read whole before any is written, so either pair may be in place.
+template <int Q, int G, int NT, int SYM, typename T>
+__device__ __forceinline__ void contract_xy(const T *src0, T *dst0, const T *src1, T *dst1, const T *__restrict__ MF,
+                                            int tid)
+{
+    using L = Lds<Q>;
+    constexpr int N1 = G * Q * Q, NPEN = 2 * N1, R = (NPEN + NT - 1) / NT;
+    constexpr int H = Q / 2, MID = Q & 1, NOH = (Q + 1) / 2;
+    T ev[R][H + MID], dv[R][H > 0 ? H : 1];
+    int base[R];
+    bool ax1[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int id = tid + r * NT;
+        base[r] = -1;
+        ax1[r] = id >= N1;
+        if (id < NPEN) {
+            const int l = ax1[r] ? id - N1 : id;
+            const int a = l % Q, t = l / Q, c = t % Q, g = t / Q;
+            // x lines start at (0, a, c), y lines at (a, 0, c); the branches keep the strides constant
+            // (with G Q^2 a multiple of 64 they are uniform across each wavefront)
+            T v[Q];
+            if (ax1[r]) {
+                base[r] = g * L::BUF + a + c * L::PLANE;
+#pragma unroll
+                for (int i = 0; i < Q; ++i) v[i] = src1[base[r] + i * L::PITCH];
+            } else {
+                base[r] = g * L::BUF + a * L::PITCH + c * L::PLANE;
+#pragma unroll
+                for (int i = 0; i < Q; ++i) v[i] = src0[base[r] + i];
+            }
+#pragma unroll
+            for (int i = 0; i < H; ++i) {
+                ev[r][i] = v[i] + v[Q - 1 - i];
+                dv[r][i] = v[i] - v[Q - 1 - i];
+            }
+            if constexpr (MID) ev[r][H] = v[H];
+        }
+    }
+    constexpr int UR = Q >= 12 ? 2 : 24 / Q;
+#pragma unroll UR
+    for (int o = 0; o < NOH; ++o) {
+        const T *row = MF + o * Q;
+        const int om = Q - 1 - o;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            if (base[r] >= 0) {
+                T E = T(0), O = T(0);
+#pragma unroll
+                for (int i = 0; i < H; ++i) {
+                    E += row[i] * ev[r][i];
+                    O += row[H + i] * dv[r][i];
+                }
+                if constexpr (MID) E += row[2 * H] * ev[r][H];
+                const T lo = E + O, hi = SYM > 0 ? E - O : O - E;
+                if (ax1[r]) {
+                    dst1[base[r] + o * L::PITCH] = lo;
+                    if (om != o) dst1[base[r] + om * L::PITCH] = hi;
+                } else {
+                    dst0[base[r] + o] = lo;
+                    if (om != o) dst0[base[r] + om] = hi;
+                }
+            }
+        }
+    }
+}
+
+// The x and y contractions of the gradient (and of its transpose) share one
+// pass over the lanes when both fit in the group together.
+constexpr bool fuse_xy(int Q, int G, int NT) { return 2 * G * Q * Q <= NT; }
+
 // Element groups.  The G elements of a group are consecutive in one x-row of
 // elements (the last group of a row may hold fewer), so elements g and g+1
 // share their face i = P-1 / i = 0.
@@ -329,8 +405,12 @@ __device__ __forceinline__ void interp(T *s0, const T *__restrict__ bas, int tid
 template <int P, int Q, int G, int NT, typename T>
 __device__ __forceinline__ void grad(T *s0, T *s1, T *s2, const T *__restrict__ bas, int tid)
 {
-    contract<0, Q, Q, Q, Q, G, NT, Q, -1>(s0, s1, bas + basis_df(P, Q), tid);
-    contract<1, Q, Q, Q, Q, G, NT, Q, -1>(s0, s2, bas + basis_df(P, Q), tid);
+    if constexpr (fuse_xy(Q, G, NT)) {
+        contract_xy<Q, G, NT, -1>(s0, s1, s0, s2, bas + basis_df(P, Q), tid);
+    } else {
+        contract<0, Q, Q, Q, Q, G, NT, Q, -1>(s0, s1, bas + basis_df(P, Q), tid);
+        contract<1, Q, Q, Q, Q, G, NT, Q, -1>(s0, s2, bas + basis_df(P, Q), tid);
+    }
     group_sync<NT>();
     contract<2, Q, Q, Q, Q, G, NT, Q, -1>(s0, s0, bas + basis_df(P, Q), tid);
     group_sync<NT>();
@@ -558,8 +638,12 @@ k_apply(const T *__restrict__ bas, const int nex, const int ney, const int nvec,
                 } else {
                     // transposed gradient: x and y lines in place, then the z lines
                     // of s0 with the x and y parts added
-                    contract<0, Q, Q, Q, Q, GV, NT, Q, -1>(s1, s1, bas + basis_dtf(P, Q), tid);
-                    contract<1, Q, Q, Q, Q, GV, NT, Q, -1>(s2, s2, bas + basis_dtf(P, Q), tid);
+                    if constexpr (fuse_xy(Q, GV, NT)) {
+                        contract_xy<Q, GV, NT, -1>(s1, s1, s2, s2, bas + basis_dtf(P, Q), tid);
+                    } else {
+                        contract<0, Q, Q, Q, Q, GV, NT, Q, -1>(s1, s1, bas + basis_dtf(P, Q), tid);
+                        contract<1, Q, Q, Q, Q, GV, NT, Q, -1>(s2, s2, bas + basis_dtf(P, Q), tid);
+                    }
                     group_sync<NT>();
                     contract<2, Q, Q, Q, Q, GV, NT, Q, -1, T, true>(s0, s0, bas + basis_dtf(P, Q), tid, s1, s2);
                     // same lines, same lanes: B^T along z follows without a sync
