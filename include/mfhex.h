@@ -102,7 +102,12 @@ typedef struct {
 
 typedef struct mfhex_op_s *mfhex_op; /* opaque; library-owned host state only */
 
-/* Validate `d` and compute sizes.  No device work. */
+/* Validate `d` and compute sizes.  No device work.  The paper defines no
+ * such call: it sizes the caller-owned storage of the operator (element
+ * restriction, the geometric factors of Sec. 2 per point, the 1D bases of
+ * Sec. 1), in the spirit of the caller-managed arrays of the libCEED
+ * interface (Sec. 2.1).  Errors: MFHEX_ERR_ARG for a null pointer or a
+ * description out of range, MFHEX_ERR_UNSUPPORTED for p > 8. */
 int mfhex_query(const mfhex_desc *d, mfhex_sizes *out);
 
 /* Set up an operator: 1D bases on the host, element restriction (int32
@@ -119,7 +124,11 @@ int mfhex_create(const mfhex_desc *d, void *workspace_dev, size_t workspace_byte
 int mfhex_destroy(mfhex_op op);
 
 /* Per-point coefficient kappa for a variable_kappa operator: device FP64
- * [n_elem][q^3], copied into the workspace (asynchronous). */
+ * [n_elem][q^3], copied into the workspace (asynchronous).  The paper is
+ * silent on coefficients; this is the reading used for the differentiable
+ * form: kappa multiplies the six geometric factors of Sec. 2 at each point,
+ * so A(kappa) stays symmetric and is linear in kappa.  MFHEX_ERR_STATE on an
+ * operator created without variable_kappa. */
 int mfhex_set_kappa(mfhex_op op, const double *kappa_dev, void *stream);
 
 /* y = A x for nvec = nrhs*ncomp columns, x and y device arrays of
@@ -134,11 +143,16 @@ int mfhex_apply(mfhex_op op, int prec, int nrhs, const void *x_dev, void *y_dev,
 int mfhex_apply_add(mfhex_op op, int prec, int nrhs, const void *x_dev, void *y_dev, void *stream);
 
 /* y = A^T x.  The operators are symmetric, so this is the same action; it is
- * the backward of mfhex_apply with respect to its input. */
+ * the backward of mfhex_apply with respect to its input.  The paper defines
+ * no adjoint; since A^e = D^T G^e D (Sec. 2) with G^e symmetric, A^T = A,
+ * and this call runs the apply kernel.  Same arguments, layout and errors as
+ * mfhex_apply. */
 int mfhex_apply_adjoint(mfhex_op op, int prec, int nrhs, const void *x_dev, void *y_dev, void *stream);
 
 /* Gradient of s = r^T (M A(kappa) M) u with respect to the per-point
- * coefficient: g[e][pt] = (Dhat M r)_pt^T G0_pt (Dhat M u)_pt, G0 the
+ * coefficient (the paper defines none; with A^e = D^T (kappa G0^e) D of
+ * Sec. 2, s is linear in each kappa_pt, and its derivative is the pointwise
+ * product below): g[e][pt] = (Dhat M r)_pt^T G0_pt (Dhat M u)_pt, G0 the
  * kappa-free geometric factors.  u, r: device FP64 [n_nodes] (ncomp = 1);
  * g: device FP64 [n_elem][q^3], overwritten.  Diffusion operators with
  * stored geometric factors only (MFHEX_ERR_UNSUPPORTED with MFHEX_FLAG_OTF).
@@ -249,7 +263,10 @@ int mfhex_mg_apply(mfhex_op op, const double *r_dev, double *z_dev, void *stream
 /* Order, node count and lambda_max(D^-1 A) estimate of level `level` (0 = finest). */
 int mfhex_mg_level(mfhex_op op, int level, int32_t *p, int64_t *n_nodes, double *lambda_max);
 
-/* Autotune the apply for (prec, nrhs): time every launch variant of the
+/* Autotune the apply for (prec, nrhs) -- the counterpart of the offline
+ * benchmark sweep that selects the best routine and batch size for the
+ * non-tensor products in MAGMA (Sec. 2.2), run here on the caller's own
+ * operator: time every launch variant of the
  * fused kernel (elements per thread group, threads per group; for the mass
  * operator also pipeline depths 1, 2 and 4) on this operator, reject any whose
  * result differs from the default configuration by more than 1e-13 (relative,
@@ -262,7 +279,8 @@ int mfhex_mg_level(mfhex_op op, int level, int32_t *p, int64_t *n_nodes, double 
 #define MFHEX_TUNE_SCRATCH(len) (3 * ((((size_t)(len)) * 8 + 255) & ~(size_t)255) + 32768)
 int mfhex_tune(mfhex_op op, int prec, int nrhs, void *scratch_dev, const char *cache_path, void *stream);
 
-/* Launch configuration the apply uses now for (prec, nrhs): the variant, the
+/* (Companions of mfhex_tune, the selection layer of Sec. 2.2.)
+ * Launch configuration the apply uses now for (prec, nrhs): the variant, the
  * elements per thread group and threads per group it stands for, and the
  * pipeline depth (element groups one thread group works through in turn,
  * loading the next group's data while it computes the current one; always 1
@@ -291,7 +309,7 @@ const char *mfhex_last_error(mfhex_op op);
 int mfhex_basis_1d(int p, int q, int quad, double *nodes, double *xq, double *wq, double *B, double *D);
 
 /* ---- Tetrahedral P_p diffusion: the non-tensor basis as a matrix product ----
- * Sec. 3 (libCEED with its MAGMA / vendor-BLAS backend): a non-tensor basis
+ * Sec. 2.1 (libCEED) and Sec. 2.2 (MAGMA, its non-tensor backend): a non-tensor basis
  * is applied through its full matrices, the gradient matrix of one element
  * (all quadrature points by all basis functions) times one column per
  * element, i.e. one matrix product for all elements (batched along the

@@ -3,7 +3,7 @@
 Plain numpy / scipy; it shares no code with the GPU library.  Only the tests
 and the benchmark's CPU leg use it.
 
-The paper (Sec. 3, libCEED and its MAGMA backend) treats non-tensor elements
+The paper (Sec. 2.1 libCEED and Sec. 2.2 MAGMA) treats non-tensor elements
 through the caller's full basis arrays: the interpolation / gradient matrix
 of one element (all quadrature points by all basis functions) is applied to
 every element, which for all elements at once is one matrix product.  This

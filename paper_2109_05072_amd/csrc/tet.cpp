@@ -1,6 +1,6 @@
 // Tetrahedral P_p diffusion operator: host set-up and C ABI.
 //
-// Sec. 3 (libCEED, MAGMA backend) applies a non-tensor basis through its full
+// Sec. 2.1 (libCEED) and Sec. 2.2 (its MAGMA backend) apply a non-tensor basis through its full
 // matrices: the interpolation / gradient matrix of one element (all points by
 // all basis functions) times the element values of every element, one matrix
 // product C = A B with A the basis matrix and B one column per element.  Here

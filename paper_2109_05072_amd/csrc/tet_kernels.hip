@@ -1,6 +1,6 @@
 // Tetrahedral P_p diffusion operator: set-up and fused apply kernels.
 //
-// Apply (Sec. 3: the non-tensor basis action as a matrix product over
+// Apply (Sec. 2.1 libCEED and Sec. 2.2 MAGMA: the non-tensor basis action as a matrix product over
 // elements).  One wavefront owns 16 elements; the kWaves wavefronts of a
 // thread group stage the basis fragments of each block of 16 quadrature
 // points b in LDS together (coalesced copies shared by 4 x 16 elements,

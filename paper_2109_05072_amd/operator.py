@@ -91,11 +91,36 @@ class Operator:
             pass
 
     # -- helpers -----------------------------------------------------------------------------
-    def _check_vec(self, t: torch.Tensor, nrhs: int):
-        if t.device.type != "cuda" or not t.is_contiguous():
-            raise ValueError("vectors must be contiguous device tensors")
-        if t.numel() != self.n_nodes * nrhs * self.ncomp:
-            raise ValueError(f"vector has {t.numel()} entries, expected {self.n_nodes * nrhs * self.ncomp}")
+    def _check_vec(self, t: torch.Tensor, nrhs: int, dtype: Optional[torch.dtype] = None, name: str = "vector",
+                   n: Optional[int] = None, device: bool = True):
+        """Raise ValueError unless t has the expected dtype and length (and, with device=True, is a
+        contiguous device tensor).
+
+        The library sizes every read and write from the precision and the node count, so a wrong
+        dtype or length would make it touch memory outside the tensor: checked before any call."""
+        if dtype is not None and t.dtype != dtype:
+            raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+        if t.dtype not in (torch.float64, torch.float32):
+            raise ValueError(f"{name} must be float64 or float32, got {t.dtype}")
+        n = self.n_nodes * nrhs * self.ncomp if n is None else n
+        if t.numel() != n:
+            raise ValueError(f"{name} has {t.numel()} entries, expected {n}")
+        if device and (t.device.type != "cuda" or not t.is_contiguous()):
+            raise ValueError(f"{name} must be a contiguous device tensor")
+
+    def _check_pair(self, x: torch.Tensor, y: torch.Tensor, nrhs: int, dtype: Optional[torch.dtype] = None,
+                    names=("x", "y"), n: Optional[int] = None):
+        """Input and output of one call: same dtype and length, both on the device, not aliased."""
+        self._check_vec(x, nrhs, dtype, names[0], n, device=False)
+        self._check_vec(y, nrhs, x.dtype, names[1], n, device=False)
+        self._check_vec(x, nrhs, dtype, names[0], n)
+        self._check_vec(y, nrhs, x.dtype, names[1], n)
+        self._check_distinct(x, y)
+
+    @staticmethod
+    def _check_distinct(x: torch.Tensor, y: torch.Tensor):
+        if x.data_ptr() == y.data_ptr():
+            raise ValueError("x and y must not alias")
 
     def _nrhs(self, x: torch.Tensor) -> int:
         per = self.n_nodes * self.ncomp
@@ -108,36 +133,34 @@ class Operator:
         """y = A x (x: [N], [N, ncomp] or [N, nrhs, ncomp]; float64 or float32)."""
         nrhs = self._nrhs(x)
         y = torch.empty_like(x) if y is None else y
-        self._check_vec(x, nrhs)
-        self._check_vec(y, nrhs)
+        self._check_pair(x, y, nrhs)
         L.mfhex_apply(self.handle, _prec(x.dtype), nrhs, x.data_ptr(), y.data_ptr(), _stream())
         return y
 
     def apply_add(self, x: torch.Tensor, y: torch.Tensor) -> torch.Tensor:
         nrhs = self._nrhs(x)
-        self._check_vec(x, nrhs)
-        self._check_vec(y, nrhs)
+        self._check_pair(x, y, nrhs)
         L.mfhex_apply_add(self.handle, _prec(x.dtype), nrhs, x.data_ptr(), y.data_ptr(), _stream())
         return y
 
     def apply_adjoint(self, x: torch.Tensor, y: Optional[torch.Tensor] = None) -> torch.Tensor:
         nrhs = self._nrhs(x)
         y = torch.empty_like(x) if y is None else y
-        self._check_vec(x, nrhs)
-        self._check_vec(y, nrhs)
+        self._check_pair(x, y, nrhs)
         L.mfhex_apply_adjoint(self.handle, _prec(x.dtype), nrhs, x.data_ptr(), y.data_ptr(), _stream())
         return y
 
     def set_kappa(self, kappa: torch.Tensor) -> None:
         kappa = kappa.contiguous()
-        if kappa.dtype != torch.float64 or kappa.numel() != self.n_elem * self.q ** 3:
-            raise ValueError("kappa must be float64 with n_elem * q^3 entries")
+        self._check_vec(kappa, 1, dtype=torch.float64, name="kappa", n=self.n_elem * self.q ** 3)
         L.mfhex_set_kappa(self.handle, kappa.data_ptr(), _stream())
 
     def kappa_grad(self, u: torch.Tensor, r: torch.Tensor) -> torch.Tensor:
         """g[e, pt] = d(r^T A(kappa) u)/d kappa[e, pt]."""
-        self._check_vec(u, 1)
-        self._check_vec(r, 1)
+        self._check_vec(u, 1, dtype=torch.float64, name="u", n=self.n_nodes, device=False)
+        self._check_vec(r, 1, dtype=torch.float64, name="r", n=self.n_nodes, device=False)
+        self._check_vec(u, 1, dtype=torch.float64, name="u", n=self.n_nodes)
+        self._check_vec(r, 1, dtype=torch.float64, name="r", n=self.n_nodes)
         g = torch.empty(self.n_elem, self.q ** 3, dtype=torch.float64, device=u.device)
         L.mfhex_kappa_grad(self.handle, u.data_ptr(), r.data_ptr(), g.data_ptr(), _stream())
         return g
@@ -161,6 +184,7 @@ class Operator:
     def rhs(self, f_q: torch.Tensor) -> torch.Tensor:
         """Load vector of a per-point forcing f_q [n_elem, q^3] (masked when Dirichlet)."""
         f_q = f_q.contiguous()
+        self._check_vec(f_q, 1, dtype=torch.float64, name="f_q", n=self.n_elem * self.q ** 3)
         b = torch.empty(self.n_nodes, dtype=torch.float64, device=f_q.device)
         L.mfhex_rhs(self.handle, f_q.data_ptr(), b.data_ptr(), _stream())
         return b
@@ -171,7 +195,9 @@ class Operator:
            exact_iters: bool = False, precond: str = "none") -> CGResult:
         """Solve A x = b by CG: mode "f64" or "mixed" (reliable updates), precond "none", "jacobi" or "mg"
         (one p-multigrid V-cycle per iteration; mg_setup first, FP64 mode)."""
-        self._check_vec(b, 1)
+        if x is not None:
+            self._check_pair(b, x, 1, dtype=torch.float64, names=("b", "x"), n=self.n_nodes)
+        self._check_vec(b, 1, dtype=torch.float64, name="b", n=self.n_nodes)
         if self._cg_work is None:
             self._cg_work = torch.empty(int(self.sizes.cg_work_bytes) + 256, dtype=torch.uint8, device=self.device)
         work = (self._cg_work.data_ptr() + 255) & ~255
@@ -205,8 +231,8 @@ class Operator:
 
     def mg_apply(self, r: torch.Tensor, z: Optional[torch.Tensor] = None) -> torch.Tensor:
         """z = M^-1 r, one V-cycle."""
-        self._check_vec(r, 1)
         z = torch.empty_like(r) if z is None else z
+        self._check_pair(r, z, 1, dtype=torch.float64, names=("r", "z"), n=self.n_nodes)
         L.mfhex_mg_apply(self.handle, r.data_ptr(), z.data_ptr(), _stream())
         return z
 

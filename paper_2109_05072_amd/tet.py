@@ -1,7 +1,7 @@
 """Python face of the tetrahedral P_p diffusion operator (``mfhex_tet_*`` in include/mfhex.h).
 
 Argument marshalling only: the set-up and the apply run in the HIP library
-(the basis action as FP64 matrix-core products, Sec. 3).  Torch provides the
+(the basis action as FP64 matrix-core products; Sec. 2.1 libCEED, Sec. 2.2 MAGMA).  Torch provides the
 device memory and the stream.
 """
 from __future__ import annotations
