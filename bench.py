@@ -18,10 +18,14 @@ oracle (dense, no sum factorization) on a bounded sample on the host cores.
 The same run times a 1 GiB device copy and reports each order's fraction of
 that measured rate next to the datasheet fraction.
 
-Prints ONE JSON line.  Extras (not part of the timed step): --cg adds FP64 vs
-mixed-precision CG (and Jacobi / p-multigrid preconditioned CG) time to a
-1e-10 relative residual; --tet adds the tetrahedral P_p apply (matrix-core
-basis products, p = 2..6) with its FP64 MFMA and HBM fractions.
+Prints ONE JSON line.  Untimed extras of the default run (skipped with
+--no-extras): the HBM ceiling from streaming kernels written for it
+(read-only sweep, copy, fill); the same BP3 sweep at about 1e8 nodes per
+order; and the second half of the metric, FP64 vs mixed-precision CG to a
+1e-10 relative residual at about 3e7 nodes, p = 3, 5, 7.  Further extras:
+--cg adds Jacobi / p-multigrid preconditioned CG; --tet adds the tetrahedral
+P_p apply (matrix-core basis products, p = 2..6) with its FP64 MFMA and HBM
+fractions.
 """
 from __future__ import annotations
 
@@ -104,7 +108,11 @@ def main():
     ap.add_argument("--adjoint", action="store_true",
                     help="also time the variable-coefficient forward / backward (p=4, 1e7 DOFs)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cg", action="store_true", help="also time FP64 vs mixed CG to 1e-10")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the untimed extras of the default run (HBM ceiling probe, the 1e8-node sweep and "
+                         "the FP64 vs mixed CG comparison)")
+    ap.add_argument("--cg", action="store_true",
+                    help="also time Jacobi- and p-multigrid-preconditioned CG next to FP64 vs mixed CG")
     ap.add_argument("--tet", action="store_true",
                     help="also time the tetrahedral P_p diffusion apply (matrix-core basis products), p=2..6")
     ap.add_argument("--tune", action="store_true", help="autotune the launch variant before timing")
@@ -233,8 +241,20 @@ def main():
         ops[p].close()
     del ops, xs, ys
     torch.cuda.empty_cache()
-    if args.cg:
-        out["cg"] = cg_compare()
+    default_extras = args.kind == "diffusion" and not args.otf and not args.no_extras
+    if default_extras:
+        # the practical HBM ceiling, measured by streaming kernels written for it (read-only sweep,
+        # copy, fill), next to the datasheet peak
+        out["hbm_ceiling"] = hbm_ceiling()
+        out["roofline"]["frac_of_read_ceiling"] = round(dom["alg_gbs"] / out["hbm_ceiling"]["read_gbs"], 4)
+        for r in per_p:
+            r["read_ceiling_frac"] = round(r["alg_gbs"] / out["hbm_ceiling"]["read_gbs"], 4)
+        # the second gate size of the sweep: about 1e8 nodes per order
+        out["per_order_1e8"] = per_order_sweep(orders, 1e8, steps=5)
+    if args.cg or default_extras:
+        # the second half of the metric: FP64 vs mixed-precision CG to a 1e-10 relative residual at
+        # about 3e7 nodes, p = 3, 5, 7 (preconditioned variants only with --cg)
+        out["cg"] = cg_compare(precond=args.cg)
     if args.batched:
         out["batched"] = batched_sweep()
     if args.tet:
@@ -263,6 +283,95 @@ def measure_copy_gbs(nbytes: int = 1 << 30, reps: int = 5) -> float:
     del a, b
     torch.cuda.empty_cache()
     return 2 * nbytes / float(np.median(ts)) / 1e9
+
+
+def hbm_ceiling(nbytes: int = 4 << 30, reps: int = 5) -> dict:
+    """Bandwidth of streaming kernels written for this measurement (libhbmprobe.so): a read-only
+    sweep, a copy and a fill of nbytes, 16-byte accesses, plain and non-temporal, over a few grid
+    sizes; the best median of each kind.  Copy counts read + write bytes."""
+    import ctypes as C
+    import torch
+    from paper_2109_05072_amd import build as libbuild
+    if not os.path.exists(libbuild.PROBE_LIB):
+        raise RuntimeError(f"{libbuild.PROBE_LIB} is not built (run __graft_entry__.build())")
+    lib = C.CDLL(libbuild.PROBE_LIB)
+    lib.hbm_stream.argtypes = [C.c_int, C.c_int, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_int, C.c_void_p]
+    lib.hbm_stream.restype = C.c_int
+    n = nbytes // 8
+    a = torch.empty(n, dtype=torch.float64, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    grids = (1024, 2048, 4096, 8192, 16384)
+    part = torch.empty(max(grids), dtype=torch.float64, device="cuda")
+    stream = torch.cuda.current_stream().cuda_stream
+    best = {}
+    for kind, name, mult in ((0, "read", 1), (1, "copy", 2), (2, "fill", 1)):
+        for nt in (0, 1):
+            for g in grids:
+                def run():
+                    rc = lib.hbm_stream(kind, nt, a.data_ptr(), b.data_ptr(), n, part.data_ptr(), g, stream)
+                    if rc != 0:
+                        raise RuntimeError(f"hbm_stream({kind}, {nt}, grid {g}) failed: {rc}")
+                run()
+                ts = []
+                for _ in range(reps):
+                    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                    e0.record()
+                    run()
+                    e1.record()
+                    torch.cuda.synchronize()
+                    ts.append(e0.elapsed_time(e1) / 1e3)
+                gbs = mult * nbytes / float(np.median(ts)) / 1e9
+                if gbs > best.get(name, (0.0,))[0]:
+                    best[name] = (gbs, {"grid": g, "nontemporal": bool(nt)})
+    # the read kernel's result checks that it really read the data
+    lib.hbm_stream(0, 0, a.data_ptr(), b.data_ptr(), n, part.data_ptr(), 1024, stream)
+    total = float(part[:1024].sum())
+    if total != float(n):
+        raise RuntimeError(f"read probe summed {total}, expected {n}")
+    del a, b, part
+    torch.cuda.empty_cache()
+    out = {f"{k}_gbs": round(v[0], 1) for k, v in best.items()}
+    out.update({f"{k}_launch": v[1] for k, v in best.items()})
+    out["bytes"] = nbytes
+    out["frac_of_peak"] = {k: round(v[0] / HBM_PEAK_GBS, 4) for k, v in best.items()}
+    return out
+
+
+def per_order_sweep(orders, dofs: float, steps: int = 5) -> list:
+    """BP3 FP64 apply at about `dofs` nodes per order (one operator at a time): median of `steps`
+    event-timed applies after two warm-ups, with the roofline fraction against 8 TB/s."""
+    import torch
+    import synth
+    import paper_2109_05072_amd as mf
+    res = []
+    for p in orders:
+        ne = synth.elems_for_dofs(dofs, p)
+        vert = synth.mesh_vertices(ne, ne, ne)
+        op = mf.Operator(ne, ne, ne, p, vert, kind="diffusion", quad="gauss", dirichlet=True)
+        x = torch.from_numpy(synth.uniform_vector(op.n_nodes)).cuda()
+        y = torch.empty_like(x)
+        for _ in range(2):
+            op.apply(x, y)
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+        for e0, e1 in ev:
+            e0.record()
+            op.apply(x, y)
+            e1.record()
+        torch.cuda.synchronize()
+        ms = float(np.median([a.elapsed_time(b) for a, b in ev]))
+        byts = alg_bytes(op.n_nodes, op.n_elem, p, p + 2)
+        gbs = byts / (ms / 1e3) / 1e9
+        cfg = op.get_config()
+        r = {"p": p, "elements_per_dim": ne, "dofs": op.n_nodes, "ms": round(ms, 4),
+             "gdofs": round(op.n_nodes / (ms / 1e3) / 1e9, 3), "alg_bytes": byts, "alg_gbs": round(gbs, 1),
+             "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
+             "launch": {"variant": cfg[0], "elements_per_group": cfg[1], "threads_per_group": cfg[2]}}
+        res.append(r)
+        print(f"# 1e8 {r}", file=sys.stderr, flush=True)
+        op.close()
+        del op, x, y, vert
+        torch.cuda.empty_cache()
+    return res
 
 
 def sweep_variants(op, x, p, reps=10, rounds=3, nrhs=1):
@@ -453,7 +562,9 @@ def tet_bench(orders=(2, 3, 4, 5, 6), dofs=1e7, reps=20):
     return res
 
 
-def cg_compare(orders=(3, 5, 7), dofs=3e7):
+def cg_compare(orders=(3, 5, 7), dofs=3e7, precond=True):
+    """FP64 CG vs mixed-precision (reliable-update) CG to a true relative residual of 1e-10 on BP3,
+    Gauss q = p+2, sin forcing; with precond also Jacobi and p-multigrid preconditioned CG."""
     import torch
     import synth
     import paper_2109_05072_amd as mf
@@ -466,6 +577,23 @@ def cg_compare(orders=(3, 5, 7), dofs=3e7):
         b = op.rhs(torch.from_numpy(f).cuda())
         r64 = op.cg(b, maxit=20000, rtol=1e-10, mode="f64")
         rmx = op.cg(b, maxit=20000, rtol=1e-10, mode="mixed")
+        d = float((rmx.x - r64.x).norm() / r64.x.norm())
+        ue = torch.from_numpy(synth.sin_solution(op.node_coords().cpu().numpy())).cuda()
+        row = {"p": p, "q": p + 2, "elements_per_dim": ne, "dofs": op.n_nodes,
+               "f64_s": round(r64.seconds, 4), "f64_iters": r64.iters, "f64_status": r64.status,
+               "mixed_s": round(rmx.seconds, 4), "mixed_iters": rmx.iters, "mixed_status": rmx.status,
+               "replacements": rmx.replacements, "fell_back_to_f64": rmx.fell_back_to_f64,
+               "speedup": round(r64.seconds / rmx.seconds, 3), "rel_diff_x_mixed_vs_f64": d,
+               "f64_rel_resid": r64.rel_resid_true, "mixed_rel_resid": rmx.rel_resid_true,
+               "max_err_vs_exact_f64": float((r64.x - ue).abs().max()),
+               "max_err_vs_exact_mixed": float((rmx.x - ue).abs().max())}
+        if not precond:
+            res.append(row)
+            print(f"# cg {row}", file=sys.stderr, flush=True)
+            op.close()
+            del op, b, r64, rmx, ue
+            torch.cuda.empty_cache()
+            continue
         j64 = op.cg(b, maxit=20000, rtol=1e-10, mode="f64", precond="jacobi")
         jmx = op.cg(b, maxit=20000, rtol=1e-10, mode="mixed", precond="jacobi")
         t0 = time.perf_counter()

@@ -55,7 +55,25 @@ def build(verbose: bool = False, jobs: int | None = None) -> str:
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")
     os.replace(tmp, LIB)
+    build_probe(verbose)
     return LIB
+
+
+PROBE_SRC = os.path.join(HERE, "probe", "hbm_stream.hip")
+PROBE_LIB = os.path.join(HERE, "libhbmprobe.so")
+
+
+def build_probe(verbose: bool = False) -> str:
+    """The HBM streaming probe (read / copy / fill kernels) the benchmark times next to the operator."""
+    tmp = PROBE_LIB + ".tmp"
+    cmd = [HIPCC] + FLAGS + ["-shared", PROBE_SRC, "-o", tmp]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"hipcc failed on {PROBE_SRC}:\n{r.stdout}\n{r.stderr}")
+    os.replace(tmp, PROBE_LIB)
+    return PROBE_LIB
 
 
 if __name__ == "__main__":

@@ -1,5 +1,5 @@
-// Tetrahedral P_p diffusion operator: the non-tensor basis path of Sec. 2.1 (libCEED) and Sec. 2.2 (MAGMA)
-// (libCEED with MAGMA / vendor BLAS): the full basis-gradient matrix of one
+// Tetrahedral P_p diffusion operator: the non-tensor basis path of Sec. 2.1 (libCEED) and
+// Sec. 2.2 (its MAGMA / vendor-BLAS backend): the full basis-gradient matrix of one
 // element is applied to all elements at once as a matrix product, here on
 // the FP64 matrix cores.  Shared between the host set-up (tet.cpp) and the
 // kernels (tet_kernels.hip).

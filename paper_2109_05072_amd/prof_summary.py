@@ -114,6 +114,52 @@ def traffic_summary(fetch_dir: str, write_dir: str, command: str) -> str:
     return "\n".join(out) + "\n"
 
 
+def counter_summary(dirs, command: str, sources=KERNEL_SOURCES) -> str:
+    """Per-kernel averages of every counter found in the ``--pmc`` runs under `dirs` (one directory per
+    pass), plus derived ratios where their inputs were collected:
+      waves_per_simd  = SQ_WAVE_CYCLES / (GRBM_GUI_ACTIVE / 8 XCDs) / 1024 SIMDs  (mean resident waves)
+      valu_busy       = SQ_ACTIVE_INST_VALU / SQ_WAVE_CYCLES x waves_per_simd  (share of SIMD cycles
+                        issuing VALU; the SQ cycle counters share one unit, so the ratio is unit-free)
+      wait_any/wave   = SQ_WAIT_ANY / SQ_WAVE_CYCLES, wait_inst_any/wave = SQ_WAIT_INST_ANY / SQ_WAVE_CYCLES
+      lds_conflict    = SQ_LDS_BANK_CONFLICT / SQ_LDS_IDX_ACTIVE
+    Counter values are per dispatch, summed over the GPU by rocprofv3."""
+    vals = defaultdict(lambda: defaultdict(list))
+    for d in dirs:
+        for r in csv.DictReader(open(_find(d, "counter_collection.csv"))):
+            vals[r["Kernel_Name"]][r["Counter_Name"]].append(float(r["Counter_Value"]))
+    names = sorted({c for k in vals for c in vals[k]})
+    out = [f"# rocprofv3 counters per dispatch (mean over dispatches)", f"# command: {command}",
+           f"# kernel source hash: {kernel_source_hash(sources)}",
+           "# derived: waves_per_simd = SQ_WAVE_CYCLES/(GRBM_GUI_ACTIVE/8)/1024; valu_busy = "
+           "SQ_ACTIVE_INST_VALU/SQ_WAVE_CYCLES*waves_per_simd; wait ratios per wave cycle; "
+           "lds_conflict = SQ_LDS_BANK_CONFLICT/SQ_LDS_IDX_ACTIVE"]
+    for k in vals:
+        sk = _short(k)
+        if not (sk.startswith("k_apply") or sk.startswith("k_mass") or sk.startswith("k_tet")):
+            continue
+        m = {c: sum(v) / len(v) for c, v in vals[k].items()}
+        out.append(f"{sk}")
+        for c in names:
+            if c in m:
+                out.append(f"    {c:<28} {m[c]:.4g}")
+        der = {}
+        if "SQ_WAVE_CYCLES" in m and "GRBM_GUI_ACTIVE" in m and m["GRBM_GUI_ACTIVE"] > 0:
+            wps = m["SQ_WAVE_CYCLES"] / (m["GRBM_GUI_ACTIVE"] / 8) / 1024
+            der["waves_per_simd"] = wps
+            if "SQ_ACTIVE_INST_VALU" in m:
+                der["valu_busy"] = m["SQ_ACTIVE_INST_VALU"] / m["SQ_WAVE_CYCLES"] * wps
+        if "SQ_WAVE_CYCLES" in m and m["SQ_WAVE_CYCLES"] > 0:
+            for c in ("SQ_WAIT_ANY", "SQ_WAIT_INST_ANY", "SQ_WAIT_INST_LDS", "SQ_ACTIVE_INST_LDS",
+                      "SQ_ACTIVE_INST_SCA", "SQ_ACTIVE_INST_VMEM", "SQ_ACTIVE_INST_VALU"):
+                if c in m:
+                    der[c.lower().replace("sq_", "") + "/wave"] = m[c] / m["SQ_WAVE_CYCLES"]
+        if "SQ_LDS_BANK_CONFLICT" in m and m.get("SQ_LDS_IDX_ACTIVE", 0) > 0:
+            der["lds_conflict"] = m["SQ_LDS_BANK_CONFLICT"] / m["SQ_LDS_IDX_ACTIVE"]
+        for c, v in der.items():
+            out.append(f"    = {c:<26} {v:.4f}")
+    return "\n".join(out) + "\n"
+
+
 def read_traffic(path: str):
     """{short kernel name: traffic bytes} if the summary matches the current kernel sources, else {}."""
     if not os.path.exists(path):
@@ -137,6 +183,9 @@ if __name__ == "__main__":
         sys.stdout.write(trace_summary(sys.argv[2], " ".join(sys.argv[3:])))
     elif mode == "trace-tet":
         sys.stdout.write(trace_summary(sys.argv[2], " ".join(sys.argv[3:]), TET_SOURCES))
+    elif mode == "counters":
+        # counters <dir1,dir2,...> <cmd...>
+        sys.stdout.write(counter_summary(sys.argv[2].split(","), " ".join(sys.argv[3:])))
     elif mode == "traffic":
         sys.stdout.write(traffic_summary(sys.argv[2], sys.argv[3], " ".join(sys.argv[4:])))
     else:

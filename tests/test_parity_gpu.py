@@ -92,15 +92,48 @@ def test_apply_fp64_matches_oracle(gpu_lib, p, kind, quad, dirichlet):
             assert relerr(y2, yo) <= TOL64
 
 
-@pytest.mark.parametrize("p", [1, 3, 5, 8])
+def _pq_id(p, quad="gauss"):
+    return f"p{p}-q{p + 2 if quad == 'gauss' else p + 1}"
+
+
+@pytest.mark.parametrize("p", range(1, 9), ids=[_pq_id(p) for p in range(1, 9)])
 @pytest.mark.parametrize("kind,quad", [("diffusion", "gauss"), ("diffusion", "gll"), ("mass", "gauss")])
-def test_apply_fp32_matches_oracle(gpu_lib, p, kind, quad):
-    _say("apply32", p, kind, quad)
-    op, pr = build(gpu_lib, 4, 3, 2, p, kind, quad, True, f32=True)
+@pytest.mark.parametrize("dirichlet", [True, False])
+def test_apply_fp32_matches_oracle(gpu_lib, p, kind, quad, dirichlet):
+    # the FP32 operator of mixed-precision CG: default launch and every FP32 launch variant the
+    # tuner may pick (the two-element FP32 defaults at q = 7 and 8 included), ragged element groups
+    _say("apply32", p, kind, quad, dirichlet)
+    op, pr = build(gpu_lib, 5, 3, 2, p, kind, quad, dirichlet, f32=True)
     x = synth.uniform_vector(pr.n_nodes)
     yo = oracle.apply(pr, x)
+    _say("apply32 default", op.get_config(torch.float32))
     y = host(op.apply(dev(x, torch.float32)))
     assert relerr(y, yo) <= TOL32
+    variants = valid_variants(op, torch.float32)
+    assert 0 in variants
+    for v in variants:
+        op.set_config(v, torch.float32)
+        _say("apply32 variant", v, op.get_config(torch.float32))
+        assert relerr(host(op.apply(dev(x, torch.float32))), yo) <= TOL32
+
+
+@pytest.mark.parametrize("p", [5, 6, 7], ids=["p5-q7-default", "p6-q8-default-two-element", "p7-q9-default"])
+def test_fp32_default_launch_at_mixed_cg_orders(gpu_lib, p):
+    # the FP32 launch defaults of their own (two-element groups at q = 7 and 8, the FP64 choice at
+    # q = 9) on a mesh whose element rows leave a ragged last group, against the oracle and
+    # against the FP64 apply rounded to FP32 accuracy
+    op, pr = build(gpu_lib, 5, 4, 3, p, "diffusion", "gauss", True, f32=True)
+    cfg = op.get_config(torch.float32)
+    _say("fp32 default", p, cfg)
+    if p in (5, 6):
+        assert cfg[1] == 2, cfg
+    x = synth.uniform_vector(pr.n_nodes, seed=9)
+    yo = oracle.apply(pr, x)
+    y32 = host(op.apply(dev(x, torch.float32)))
+    y64 = host(op.apply(dev(x)))
+    print("fp32 default", p, cfg, "err vs oracle", relerr(y32, yo))
+    assert relerr(y32, yo) <= TOL32
+    assert relerr(y64, yo) <= TOL64
 
 
 @pytest.mark.parametrize("p,ncomp,nrhs", [(2, 3, 1), (3, 1, 4), (5, 3, 2), (8, 1, 3), (4, 3, 8)])
@@ -335,8 +368,9 @@ def test_config0_fifty_cg_iterations_match_oracle(gpu_lib):
     xg = host(res.x)
     print("config0 x50 rel diff", relerr(xg, xo), "history max rel diff", relerr(res.history, ho))
     assert res.iters == 50
-    assert relerr(xg, xo) <= 1e-10
-    assert np.all(np.abs(res.history - ho) <= 1e-10 * ho + 1e-14 * ho[0])
+    # the stated FP64 target; the measured agreement is printed above (round-off level, 1e-15)
+    assert relerr(xg, xo) <= 1e-12
+    assert np.all(np.abs(res.history - ho) <= 1e-12 * ho + 1e-14 * ho[0])
 
 
 def _masked_rhs(op, pr):
@@ -367,6 +401,93 @@ def test_cg_solution_and_mixed_precision(gpu_lib, p):
     # discretization error against the exact solution is far above the solver error
     ue = synth.sin_solution(host(op.node_coords()))
     assert np.abs(x64 - ue).max() < 1e-2
+
+
+@pytest.mark.parametrize("p,ne", [(5, 4), (7, 3)], ids=["p5-q7", "p7-q9"])
+def test_mixed_cg_at_high_order_matches_oracle(gpu_lib, p, ne):
+    # mixed-precision CG at two of the mixed-CG orders (FP32 operator at q = 7 and q = 9): the
+    # oracle's own operator confirms the true residual of the GPU solution, and the solution is
+    # compared with the oracle's CG solve of the oracle's load vector
+    op, pr = build(gpu_lib, ne, ne, ne, p, "diffusion", "gauss", True, f32=True, rhs=True)
+    b = _masked_rhs(op, pr)
+    bo = oracle.rhs(pr, synth.sin_forcing(oracle.qpoint_geometry(pr)[0]))
+    assert relerr(host(b), bo) <= TOL64
+    rmx = op.cg(b, maxit=20000, rtol=1e-10, mode="mixed")
+    r64 = op.cg(b, maxit=20000, rtol=1e-10, mode="f64")
+    assert rmx.status == 0 and rmx.rel_resid_true <= 1e-10
+    assert r64.status == 0 and r64.rel_resid_true <= 1e-10
+    xmx, x64 = host(rmx.x), host(r64.x)
+    res_orc = float(np.linalg.norm(bo - oracle.apply(pr, xmx)) / np.linalg.norm(bo))
+    xo, _, _, code = oracle.cg(pr, bo, maxit=20000, rtol=1e-13)
+    assert code == oracle.OK
+    e_mx, e_64 = relerr(xmx, xo), relerr(x64, xo)
+    print(f"mixed p={p}: {rmx.iters} it, {rmx.replacements} replacements, fallback {rmx.fell_back_to_f64}, "
+          f"true residual (library) {rmx.rel_resid_true:.3e}, (oracle operator) {res_orc:.3e}, "
+          f"err vs oracle CG {e_mx:.3e} (FP64 CG {e_64:.3e})", flush=True)
+    # the oracle's operator sees the residual the library reports (to rounding of the two applies)
+    assert res_orc <= 1.01e-10
+    # both solutions sit within the solver tolerance of the oracle's, amplified by the condition
+    # number of these small meshes (measured errors are printed above)
+    assert e_mx <= 1e-6 and e_64 <= 1e-6
+
+
+# --- CG status paths --------------------------------------------------------------------------
+
+def test_cg_reports_maxit_as_noconv(gpu_lib):
+    from paper_2109_05072_amd import _lib as L
+    op, pr = build(gpu_lib, 4, 4, 4, 2, f32=True)
+    b = dev(synth.uniform_vector(pr.n_nodes, seed=3) * interior_mask(pr))
+    for mode in ("f64", "mixed"):
+        res = op.cg(b, maxit=7, rtol=1e-14, mode=mode)
+        print("noconv", mode, res.status, res.iters, res.rel_resid_true)
+        assert res.status == L.MFHEX_ERR_NOCONV
+        assert res.iters == 7
+        # x and the statistics stay valid: the reported residual is that of the returned x
+        xo = host(res.x)
+        true = float(np.linalg.norm(host(b) - oracle.apply(pr, xo)) / np.linalg.norm(host(b)))
+        assert abs(true - res.rel_resid_true) <= 1e-8 * true
+        assert 1e-14 < res.rel_resid_true < 1.0
+
+
+def test_cg_non_finite_rhs_is_breakdown(gpu_lib):
+    from paper_2109_05072_amd import _lib as L
+    op, pr = build(gpu_lib, 3, 3, 3, 2, f32=True)
+    bh = synth.uniform_vector(pr.n_nodes, seed=3) * interior_mask(pr)
+    bh[pr.n_nodes // 2] = np.nan
+    for mode in ("f64", "mixed"):
+        with pytest.raises(L.MFHexError) as ei:
+            op.cg(dev(bh), maxit=50, rtol=1e-10, mode=mode)
+        assert ei.value.code == L.MFHEX_ERR_BREAKDOWN
+
+
+def test_cg_negative_coefficient_is_breakdown(gpu_lib):
+    # kappa < 0 makes the operator negative definite: p^T A p < 0 at the first iteration
+    from paper_2109_05072_amd import _lib as L
+    op, pr = build(gpu_lib, 3, 3, 3, 2, vark=True)
+    op.set_kappa(-torch.ones(op.n_elem * op.q ** 3, dtype=torch.float64, device="cuda"))
+    b = dev(synth.uniform_vector(pr.n_nodes, seed=3) * interior_mask(pr))
+    with pytest.raises(L.MFHexError) as ei:
+        op.cg(b, maxit=50, rtol=1e-10)
+    assert ei.value.code == L.MFHEX_ERR_BREAKDOWN
+    # the same operator with kappa > 0 converges
+    op.set_kappa(torch.ones(op.n_elem * op.q ** 3, dtype=torch.float64, device="cuda"))
+    assert op.cg(b, maxit=500, rtol=1e-10).status == 0
+
+
+def test_mixed_cg_falls_back_to_fp64_when_replacements_stall(gpu_lib):
+    # a tolerance below FP64 round-off: the true residual stops falling near 1e-16, three residual
+    # replacements in a row without progress hand the solve to FP64 CG, which then runs to maxit
+    from paper_2109_05072_amd import _lib as L
+    op, pr = build(gpu_lib, 3, 3, 3, 2, f32=True)
+    b = dev(synth.uniform_vector(pr.n_nodes, seed=3) * interior_mask(pr))
+    res = op.cg(b, maxit=1500, rtol=1e-17, mode="mixed", replace_every=20)
+    print("fallback", res.status, res.iters, res.replacements, res.fell_back_to_f64, res.rel_resid_true)
+    assert res.fell_back_to_f64
+    assert res.status == L.MFHEX_ERR_NOCONV and res.iters == 1500
+    assert res.replacements >= 3
+    assert res.rel_resid_true <= 1e-13
+    xo, _, _, _ = oracle.cg(pr, host(b), maxit=1500, rtol=1e-14)
+    assert relerr(host(res.x), xo) <= 1e-11
 
 
 # --- geometric factors evaluated in the kernel (no stored factors) ---------------------------
@@ -450,8 +571,8 @@ def test_config0_fifty_pcg_iterations_match_oracle(gpu_lib):
     xg = host(res.x)
     print("config0 pcg x50 rel diff", relerr(xg, xo), "history max rel diff", relerr(res.history, ho))
     assert res.iters == 50
-    assert relerr(xg, xo) <= 1e-10
-    assert np.all(np.abs(res.history - ho) <= 1e-10 * ho + 1e-14 * ho[0])
+    assert relerr(xg, xo) <= 1e-12
+    assert np.all(np.abs(res.history - ho) <= 1e-12 * ho + 1e-14 * ho[0])
 
 
 @pytest.mark.parametrize("p", [2, 3])
