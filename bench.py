@@ -382,7 +382,7 @@ def sweep_variants(op, x, p, reps=10, rounds=3, nrhs=1):
     default = op.get_config(nrhs=nrhs)
     depths = (1, 2, 4) if op.kind == "mass" else (1,)
     cfgs = []
-    for v in range(9):
+    for v in range(15):
         for d in depths:
             try:
                 op.set_config(v, nrhs=nrhs, groups_per_block=d)

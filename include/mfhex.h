@@ -73,6 +73,14 @@ enum { MFHEX_PRECOND_NONE = 0, MFHEX_PRECOND_JACOBI = 1, MFHEX_PRECOND_MG = 2 };
                             * vertices (the factors equal the stored ones up to rounding).  The
                             * workspace then holds no factor array; mfhex_diagonal (and so the
                             * Jacobi-preconditioned CG) is not available on such an operator. */
+#define MFHEX_FLAG_DETERMINISTIC 8u /* results that do not depend on the order in which element groups run
+                            * (a reference for checks of the atomic path, e.g. run-to-run spread): the
+                            * apply stores every element's values (plain stores) in a workspace buffer
+                            * of n_elem (p+1)^3 ncomp FP64 values, and a second kernel sums each node's
+                            * (up to 8) element values in increasing element order.  The paper's
+                            * operator is the same (E->L scatter-add, Sec. 2, A_L = sum R^T A^e R);
+                            * only the summation order is fixed.  One right-hand side per apply
+                            * (nrhs = 1, else MFHEX_ERR_UNSUPPORTED); the load vector keeps atomics. */
 
 /* Operator description.
  *   p in [1,8].  quad = MFHEX_GAUSS needs q = p+2 (mass and stiffness);
@@ -288,8 +296,11 @@ int mfhex_tune(mfhex_op op, int prec, int nrhs, void *scratch_dev, const char *c
 int mfhex_get_config(mfhex_op op, int prec, int nrhs, int32_t *variant, int32_t *elems_per_group,
                      int32_t *threads_per_group, int32_t *groups_per_block);
 
-/* Force the launch configuration for (prec, nrhs): variant 0 .. 8 (5 .. 8
- * carry 2, 4, 8, 16 vectors of a multi-vector together) and pipeline depth
+/* Force the launch configuration for (prec, nrhs): variant 0 .. 14 (5 .. 8
+ * carry 2, 4, 8, 16 vectors of a multi-vector together; 9 .. 14 are the
+ * factored-gradient diffusion kernel for Gauss points, which forms the
+ * gradient with the basis derivative at the points in three contraction
+ * stages instead of six) and pipeline depth
  * groups_per_block (0: the operator's default, measured per order for mass
  * and 1 for diffusion; mass accepts 1 .. 64, diffusion only 1).
  * MFHEX_ERR_ARG if out of range. */

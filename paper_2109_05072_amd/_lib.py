@@ -26,7 +26,7 @@ MFHEX_GAUSS, MFHEX_GLL = 0, 1
 MFHEX_F64, MFHEX_F32 = 0, 1
 MFHEX_CG_F64, MFHEX_CG_MIXED = 0, 1
 MFHEX_PRECOND_NONE, MFHEX_PRECOND_JACOBI, MFHEX_PRECOND_MG = 0, 1, 2
-MFHEX_FLAG_F32, MFHEX_FLAG_RHS, MFHEX_FLAG_OTF = 1, 2, 4
+MFHEX_FLAG_F32, MFHEX_FLAG_RHS, MFHEX_FLAG_OTF, MFHEX_FLAG_DETERMINISTIC = 1, 2, 4, 8
 
 # every symbol include/mfhex.h declares
 EXPORTS = (

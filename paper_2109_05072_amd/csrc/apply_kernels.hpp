@@ -363,13 +363,38 @@ __device__ __forceinline__ void gather(T *s0, const int32_t (&off)[NR], const T 
 // Transposed restriction: y[node][v0 + vc] += element values (both elements'
 // values summed for a face shared inside the group) for unmasked nodes, with
 // hardware atomics (nodes on the group boundary are shared with other groups).
+//
+// Deterministic form (ebuf non-null): no atomics; every element stores its own
+// values at ebuf[(e P^3 + local node) nvec + vector] with plain stores (a face
+// node shared inside the group is stored once for each of its two elements),
+// and k_det_assemble later sums each node's element values in a fixed order.
 template <int P, int Q, int G, int NT, int VC, typename T, int NR>
 __device__ __forceinline__ void scatter_add(const T *s0, const int32_t (&off)[NR], T *__restrict__ y, int nvec, int v0,
-                                            int nvalid, int tid)
+                                            int nvalid, int tid, T *__restrict__ ebuf = nullptr, int64_t e0 = 0)
 {
     static_assert(NR == NodeIO<P, G, NT, VC>::NR, "offset count");
     using L = Lds<Q>;
     using IO = NodeIO<P, G, NT, VC>;
+    if (ebuf) {
+        constexpr int P3 = P * P * P;
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+            const int id = tid + r * NT;
+            const int vc = id % VC;
+            if (off[r] >= 0 && v0 + vc < nvec) {
+                const int u = id / VC, line = u / IO::W, X = u - line * IO::W;
+                int g, i;
+                line_pos<P, G>(X, nvalid, g, i);
+                const int jk = L::PITCH * (line % P) + L::PLANE * (line / P);
+                const int ljk = P * line;  // P (j + P k)
+                ebuf[((e0 + g) * P3 + i + ljk) * nvec + v0 + vc] = s0[(g * VC + vc) * L::BUF + i + jk];
+                if (G > 1 && i == 0 && g > 0)
+                    ebuf[((e0 + g - 1) * P3 + (P - 1) + ljk) * nvec + v0 + vc] =
+                        s0[((g - 1) * VC + vc) * L::BUF + (P - 1) + jk];
+            }
+        }
+        return;
+    }
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
         const int id = tid + r * NT;
@@ -446,7 +471,7 @@ template <int P, int Q, bool COLLOC, int MODE, bool VARK, typename T, int G, int
 __global__ void __launch_bounds__(NT)
 k_apply(const T *__restrict__ bas, const int nex, const int ney, const int nvec, const int32_t *__restrict__ offsets,
         const T *__restrict__ qdata, const double *__restrict__ kappa, const double *__restrict__ wdet,
-        const double *__restrict__ vert, const T *__restrict__ x, T *__restrict__ y)
+        const double *__restrict__ vert, const T *__restrict__ x, T *__restrict__ y, T *__restrict__ ebuf)
 {
     constexpr int Q2 = Q * Q, Q3 = Q2 * Q;
     constexpr int NPT = G * Q3, RQ = (NPT + NT - 1) / NT;
@@ -669,7 +694,7 @@ k_apply(const T *__restrict__ bas, const int nex, const int ney, const int nvec,
             }
         }
         group_sync<NT>();
-        scatter_add<P, Q, G, NT, VC, T>(sout, off, y, nvec, v0, nvalid, tid);
+        scatter_add<P, Q, G, NT, VC, T>(sout, off, y, nvec, v0, nvalid, tid, ebuf, e0);
         group_sync<NT>();
     }
 }
@@ -701,7 +726,8 @@ __device__ __forceinline__ void load_mass_weights(T (&w)[RQ], const T *__restric
 template <int P, int Q, bool COLLOC, typename T, int G, int NT, int VC>
 __global__ void __launch_bounds__(NT)
 k_mass(const T *__restrict__ bas, const int nex, const int64_t ngroups, const int nvec, const int chain,
-       const int32_t *__restrict__ offsets, const T *__restrict__ qdata, const T *__restrict__ x, T *__restrict__ y)
+       const int32_t *__restrict__ offsets, const T *__restrict__ qdata, const T *__restrict__ x, T *__restrict__ y,
+       T *__restrict__ ebuf)
 {
     constexpr int Q2 = Q * Q, Q3 = Q2 * Q;
     constexpr int NPT = G * Q3, RQ = (NPT + NT - 1) / NT;
@@ -763,7 +789,7 @@ k_mass(const T *__restrict__ bas, const int nex, const int64_t ngroups, const in
             contract<0, Q, P, P, P, GV, NT, Q, 1>(s0, s0, bas + basis_btf(P, Q), tid);
         }
         group_sync<NT>();
-        scatter_add<P, Q, G, NT, VC, T>(s0, off, y, nvec, v0, gpos.nvalid, tid);
+        scatter_add<P, Q, G, NT, VC, T>(s0, off, y, nvec, v0, gpos.nvalid, tid, ebuf, gpos.e0);
         group_sync<NT>();
         if (!more) break;
         if (newgrp) {
@@ -831,6 +857,380 @@ k_kgrad(const double *__restrict__ bas, const int64_t nelem, const int32_t *__re
 }
 
 // ---------------------------------------------------------------------------
+// y += A x (diffusion, Gauss points, q = p+2) with the gradient factored
+// through the basis derivative at the points, G[a][i] = l_i'(x_a):
+//   u_r = (G (x) B (x) B) u,  u_s = (B (x) G (x) B) u,  u_t = (B (x) B (x) G) u
+// (x fastest in the Kronecker products), and back
+//   y = (G^T B^T B^T) v_r + (B^T G^T B^T) v_s + (B^T B^T G^T) v_t.
+// Sharing the partial products, the whole operator is six contraction
+// stages instead of twelve: z (B u and G u), y (B and G of the first, B of
+// the second), x (G, B, B), then the pointwise factors, and x (G^T, B^T,
+// B^T), y (B^T + G^T, B^T), z (B^T + G^T).  Each stage reads every line it
+// owns once from LDS and forms two or three contractions from it, so there
+// are half as many stage barriers and about 40% less LDS traffic, at the
+// cost of about 20% more multiply-adds (G is Q x P where the collocated
+// derivative D is Q x Q, but it is applied to P-long lines).  Same element
+// groups, restriction, even-odd folding and factor prefetch as k_apply.
+// ---------------------------------------------------------------------------
+
+// One line of NI values, folded: e_i = v_i + v_{NI-1-i}, d_i = v_i - v_{NI-1-i} (i < NI/2), e_{NI/2} = v_mid.
+template <int NI, typename T>
+struct FLine {
+    static constexpr int H = NI / 2, MID = NI & 1;
+    T e[H + MID];
+    T d[H > 0 ? H : 1];
+};
+
+template <int NI, int ST, typename T>
+__device__ __forceinline__ void fold_line(const T *src, int base, FLine<NI, T> &f)
+{
+    constexpr int H = NI / 2;
+    T v[NI];
+#pragma unroll
+    for (int i = 0; i < NI; ++i) v[i] = src[base + i * ST];
+#pragma unroll
+    for (int i = 0; i < H; ++i) {
+        f.e[i] = v[i] + v[NI - 1 - i];
+        f.d[i] = v[i] - v[NI - 1 - i];
+    }
+    if constexpr (NI & 1) f.e[H] = v[H];
+}
+
+// Even and odd half-sums of one folded row against a folded line: out_o = E + O and
+// out_{NO-1-o} = SYM (E - O).
+template <int NI, typename T>
+__device__ __forceinline__ void fdot(const T *__restrict__ row, const FLine<NI, T> &f, T &E, T &O)
+{
+    constexpr int H = NI / 2;
+    E = T(0);
+    O = T(0);
+#pragma unroll
+    for (int i = 0; i < H; ++i) {
+        E += row[i] * f.e[i];
+        O += row[H + i] * f.d[i];
+    }
+    if constexpr (NI & 1) E += row[2 * H] * f.e[H];
+}
+
+// Lines along axis AX of G element arrays with extents (E0, E1, E2) (same lane-to-line order as contract()).
+template <int AX, int E0, int E1, int E2, int G, int NT, int Q>
+struct LineSet {
+    using L = Lds<Q>;
+    static constexpr int NI = AX == 0 ? E0 : AX == 1 ? E1 : E2;
+    static constexpr int NA = AX == 0 ? E1 : E0;
+    static constexpr int NB = AX == 2 ? E1 : E2;
+    static constexpr int SA = AX == 0 ? L::PITCH : 1;
+    static constexpr int SB = AX == 2 ? L::PITCH : L::PLANE;
+    static constexpr int ST = AX == 0 ? 1 : AX == 1 ? L::PITCH : L::PLANE;
+    static constexpr int NPEN = G * NA * NB;
+    static constexpr int R = (NPEN + NT - 1) / NT;
+    __device__ static __forceinline__ int base(int id)
+    {
+        const int a = id % NA, t = id / NA, b = t % NB, g = t / NB;
+        return g * L::BUF + a * SA + b * SB;
+    }
+};
+
+// Forward z: A (nodes) -> A = B_z u, Bb = G_z u.
+template <int P, int Q, int G, int NT, typename T>
+__device__ __forceinline__ void gf_z(T *A, T *Bb, const T *__restrict__ bas, int tid)
+{
+    using LS = LineSet<2, P, P, P, G, NT, Q>;
+    constexpr int NOH = (Q + 1) / 2, UR = 2;
+    FLine<P, T> f[LS::R];
+    int base[LS::R];
+#pragma unroll
+    for (int r = 0; r < LS::R; ++r) {
+        const int id = tid + r * NT;
+        base[r] = id < LS::NPEN ? LS::base(id) : -1;
+        if (base[r] >= 0) fold_line<P, LS::ST>(A, base[r], f[r]);
+    }
+    const T *bf = bas + basis_bf(P, Q), *gf = bas + basis_gf(P, Q);
+#pragma unroll UR
+    for (int o = 0; o < NOH; ++o) {
+        const int om = Q - 1 - o;
+#pragma unroll
+        for (int r = 0; r < LS::R; ++r) {
+            if (base[r] < 0) continue;
+            T E, O;
+            fdot<P>(bf + o * P, f[r], E, O);
+            A[base[r] + o * LS::ST] = E + O;
+            if (om != o) A[base[r] + om * LS::ST] = E - O;
+            fdot<P>(gf + o * P, f[r], E, O);
+            Bb[base[r] + o * LS::ST] = E + O;
+            if (om != o) Bb[base[r] + om * LS::ST] = O - E;
+        }
+    }
+}
+
+// Forward y: A (B_z u), Bb (G_z u) -> A = B_y A, C = G_y A, Bb = B_y Bb.
+template <int P, int Q, int G, int NT, typename T>
+__device__ __forceinline__ void gf_y(T *A, T *Bb, T *C, const T *__restrict__ bas, int tid)
+{
+    using LS = LineSet<1, P, P, Q, G, NT, Q>;
+    constexpr int NOH = (Q + 1) / 2, UR = 2;
+    FLine<P, T> fa[LS::R], fb[LS::R];
+    int base[LS::R];
+#pragma unroll
+    for (int r = 0; r < LS::R; ++r) {
+        const int id = tid + r * NT;
+        base[r] = id < LS::NPEN ? LS::base(id) : -1;
+        if (base[r] >= 0) {
+            fold_line<P, LS::ST>(A, base[r], fa[r]);
+            fold_line<P, LS::ST>(Bb, base[r], fb[r]);
+        }
+    }
+    const T *bf = bas + basis_bf(P, Q), *gf = bas + basis_gf(P, Q);
+#pragma unroll UR
+    for (int o = 0; o < NOH; ++o) {
+        const int om = Q - 1 - o;
+#pragma unroll
+        for (int r = 0; r < LS::R; ++r) {
+            if (base[r] < 0) continue;
+            T E, O;
+            fdot<P>(bf + o * P, fa[r], E, O);
+            A[base[r] + o * LS::ST] = E + O;
+            if (om != o) A[base[r] + om * LS::ST] = E - O;
+            fdot<P>(gf + o * P, fa[r], E, O);
+            C[base[r] + o * LS::ST] = E + O;
+            if (om != o) C[base[r] + om * LS::ST] = O - E;
+            fdot<P>(bf + o * P, fb[r], E, O);
+            Bb[base[r] + o * LS::ST] = E + O;
+            if (om != o) Bb[base[r] + om * LS::ST] = E - O;
+        }
+    }
+}
+
+// Forward x: A, C, Bb -> A = G_x A (d/dr), C = B_x C (d/ds), Bb = B_x Bb (d/dt), all at the points.
+template <int P, int Q, int G, int NT, typename T>
+__device__ __forceinline__ void gf_x(T *A, T *Bb, T *C, const T *__restrict__ bas, int tid)
+{
+    using LS = LineSet<0, P, Q, Q, G, NT, Q>;
+    constexpr int NOH = (Q + 1) / 2, UR = 1;
+    FLine<P, T> fa[LS::R], fb[LS::R], fc[LS::R];
+    int base[LS::R];
+#pragma unroll
+    for (int r = 0; r < LS::R; ++r) {
+        const int id = tid + r * NT;
+        base[r] = id < LS::NPEN ? LS::base(id) : -1;
+        if (base[r] >= 0) {
+            fold_line<P, LS::ST>(A, base[r], fa[r]);
+            fold_line<P, LS::ST>(Bb, base[r], fb[r]);
+            fold_line<P, LS::ST>(C, base[r], fc[r]);
+        }
+    }
+    const T *bf = bas + basis_bf(P, Q), *gf = bas + basis_gf(P, Q);
+#pragma unroll UR
+    for (int o = 0; o < NOH; ++o) {
+        const int om = Q - 1 - o;
+#pragma unroll
+        for (int r = 0; r < LS::R; ++r) {
+            if (base[r] < 0) continue;
+            T E, O;
+            fdot<P>(gf + o * P, fa[r], E, O);
+            A[base[r] + o] = E + O;
+            if (om != o) A[base[r] + om] = O - E;
+            fdot<P>(bf + o * P, fc[r], E, O);
+            C[base[r] + o] = E + O;
+            if (om != o) C[base[r] + om] = E - O;
+            fdot<P>(bf + o * P, fb[r], E, O);
+            Bb[base[r] + o] = E + O;
+            if (om != o) Bb[base[r] + om] = E - O;
+        }
+    }
+}
+
+// Transposed x: A (v_r), C (v_s), Bb (v_t) at the points -> A = G_x^T A, C = B_x^T C, Bb = B_x^T Bb.
+template <int P, int Q, int G, int NT, typename T>
+__device__ __forceinline__ void gf_xt(T *A, T *Bb, T *C, const T *__restrict__ bas, int tid)
+{
+    using LS = LineSet<0, Q, Q, Q, G, NT, Q>;
+    constexpr int NOH = (P + 1) / 2, UR = 1;
+    FLine<Q, T> fa[LS::R], fb[LS::R], fc[LS::R];
+    int base[LS::R];
+#pragma unroll
+    for (int r = 0; r < LS::R; ++r) {
+        const int id = tid + r * NT;
+        base[r] = id < LS::NPEN ? LS::base(id) : -1;
+        if (base[r] >= 0) {
+            fold_line<Q, LS::ST>(A, base[r], fa[r]);
+            fold_line<Q, LS::ST>(Bb, base[r], fb[r]);
+            fold_line<Q, LS::ST>(C, base[r], fc[r]);
+        }
+    }
+    const T *btf = bas + basis_btf(P, Q), *gtf = bas + basis_gtf(P, Q);
+#pragma unroll UR
+    for (int o = 0; o < NOH; ++o) {
+        const int om = P - 1 - o;
+#pragma unroll
+        for (int r = 0; r < LS::R; ++r) {
+            if (base[r] < 0) continue;
+            T E, O;
+            fdot<Q>(gtf + o * Q, fa[r], E, O);
+            A[base[r] + o] = E + O;
+            if (om != o) A[base[r] + om] = O - E;
+            fdot<Q>(btf + o * Q, fc[r], E, O);
+            C[base[r] + o] = E + O;
+            if (om != o) C[base[r] + om] = E - O;
+            fdot<Q>(btf + o * Q, fb[r], E, O);
+            Bb[base[r] + o] = E + O;
+            if (om != o) Bb[base[r] + om] = E - O;
+        }
+    }
+}
+
+// Transposed y: A, C, Bb (nodes along x, points along y and z) -> A = B_y^T A + G_y^T C, Bb = B_y^T Bb.
+template <int P, int Q, int G, int NT, typename T>
+__device__ __forceinline__ void gf_yt(T *A, T *Bb, const T *C, const T *__restrict__ bas, int tid)
+{
+    using LS = LineSet<1, P, Q, Q, G, NT, Q>;
+    constexpr int NOH = (P + 1) / 2, UR = 1;
+    FLine<Q, T> fa[LS::R], fb[LS::R], fc[LS::R];
+    int base[LS::R];
+#pragma unroll
+    for (int r = 0; r < LS::R; ++r) {
+        const int id = tid + r * NT;
+        base[r] = id < LS::NPEN ? LS::base(id) : -1;
+        if (base[r] >= 0) {
+            fold_line<Q, LS::ST>(A, base[r], fa[r]);
+            fold_line<Q, LS::ST>(Bb, base[r], fb[r]);
+            fold_line<Q, LS::ST>(C, base[r], fc[r]);
+        }
+    }
+    const T *btf = bas + basis_btf(P, Q), *gtf = bas + basis_gtf(P, Q);
+#pragma unroll UR
+    for (int o = 0; o < NOH; ++o) {
+        const int om = P - 1 - o;
+#pragma unroll
+        for (int r = 0; r < LS::R; ++r) {
+            if (base[r] < 0) continue;
+            T E1, O1, E2, O2;
+            fdot<Q>(btf + o * Q, fa[r], E1, O1);
+            fdot<Q>(gtf + o * Q, fc[r], E2, O2);
+            A[base[r] + o * LS::ST] = (E1 + O1) + (E2 + O2);
+            if (om != o) A[base[r] + om * LS::ST] = (E1 - O1) + (O2 - E2);
+            fdot<Q>(btf + o * Q, fb[r], E1, O1);
+            Bb[base[r] + o * LS::ST] = E1 + O1;
+            if (om != o) Bb[base[r] + om * LS::ST] = E1 - O1;
+        }
+    }
+}
+
+// Transposed z: A, Bb (nodes along x and y, points along z) -> A = B_z^T A + G_z^T Bb (element values).
+template <int P, int Q, int G, int NT, typename T>
+__device__ __forceinline__ void gf_zt(T *A, const T *Bb, const T *__restrict__ bas, int tid)
+{
+    using LS = LineSet<2, P, P, Q, G, NT, Q>;
+    constexpr int NOH = (P + 1) / 2, UR = 2;
+    FLine<Q, T> fa[LS::R], fb[LS::R];
+    int base[LS::R];
+#pragma unroll
+    for (int r = 0; r < LS::R; ++r) {
+        const int id = tid + r * NT;
+        base[r] = id < LS::NPEN ? LS::base(id) : -1;
+        if (base[r] >= 0) {
+            fold_line<Q, LS::ST>(A, base[r], fa[r]);
+            fold_line<Q, LS::ST>(Bb, base[r], fb[r]);
+        }
+    }
+    const T *btf = bas + basis_btf(P, Q), *gtf = bas + basis_gtf(P, Q);
+#pragma unroll UR
+    for (int o = 0; o < NOH; ++o) {
+        const int om = P - 1 - o;
+#pragma unroll
+        for (int r = 0; r < LS::R; ++r) {
+            if (base[r] < 0) continue;
+            T E1, O1, E2, O2;
+            fdot<Q>(btf + o * Q, fa[r], E1, O1);
+            fdot<Q>(gtf + o * Q, fb[r], E2, O2);
+            A[base[r] + o * LS::ST] = (E1 + O1) + (E2 + O2);
+            if (om != o) A[base[r] + om * LS::ST] = (E1 - O1) + (O2 - E2);
+        }
+    }
+}
+
+// PF: the lane's geometric factors are loaded at the start of the element group (as in k_apply);
+// otherwise in the pointwise stage, keeping their registers free through the forward stages.
+template <int P, int Q, bool VARK, typename T, int G, int NT, bool PF>
+__global__ void __launch_bounds__(NT)
+k_apply_gf(const T *__restrict__ bas, const int nex, const int nvec, const int32_t *__restrict__ offsets,
+           const T *__restrict__ qdata, const double *__restrict__ kappa, const T *__restrict__ x, T *__restrict__ y,
+           T *__restrict__ ebuf)
+{
+    constexpr int Q2 = Q * Q, Q3 = Q2 * Q;
+    constexpr int NPT = G * Q3, RQ = (NPT + NT - 1) / NT;
+    using L = Lds<Q>;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T *const A = reinterpret_cast<T *>(smem_raw);
+    T *const Bb = A + G * L::BUF;
+    T *const C = Bb + G * L::BUF;
+    const int tid = threadIdx.x;
+    const GroupPos gpos = group_pos<G>(xcd_block(blockIdx.x, gridDim.x), nex);
+    const int64_t e0 = gpos.e0;
+    const int nvalid = gpos.nvalid;
+
+    int32_t off[NodeIO<P, G, NT, 1>::NR];
+    load_offsets<P, G, NT, 1>(off, offsets, e0, nvalid, tid);
+
+    // factors of the points of this lane (elements past the end of the row read the first element's)
+    auto load_factors = [&](T (&qv)[RQ][kQdDiff]) {
+#pragma unroll
+        for (int k = 0; k < RQ; ++k) {
+            const int id = tid + k * NT < NPT ? tid + k * NT : NPT - 1;
+            const int g = id / Q3, pt = id - g * Q3;
+            const int64_t e = g < nvalid ? e0 + g : e0;
+            const T *qd = qdata + e * (kQdDiff * Q3) + pt;
+#pragma unroll
+            for (int m = 0; m < kQdDiff; ++m) qv[k][m] = __builtin_nontemporal_load(&qd[m * Q3]);
+            if constexpr (VARK) {
+                const T kap = T(kappa[e * Q3 + pt]);
+#pragma unroll
+                for (int m = 0; m < kQdDiff; ++m) qv[k][m] *= kap;
+            }
+        }
+    };
+    T qv[RQ][kQdDiff];
+    if constexpr (PF) load_factors(qv);
+
+    for (int v0 = 0; v0 < nvec; ++v0) {
+        gather<P, Q, G, NT, 1, T>(A, off, x, nvec, v0, nvalid, tid);
+        group_sync<NT>();
+        gf_z<P, Q, G, NT, T>(A, Bb, bas, tid);
+        group_sync<NT>();
+        gf_y<P, Q, G, NT, T>(A, Bb, C, bas, tid);
+        if constexpr (!PF) {
+            if (v0 == 0) load_factors(qv);
+        }
+        group_sync<NT>();
+        gf_x<P, Q, G, NT, T>(A, Bb, C, bas, tid);
+        group_sync<NT>();
+#pragma unroll
+        for (int k = 0; k < RQ; ++k) {
+            const int id = tid + k * NT;
+            if (id < NPT) {
+                const int g = id / Q3, pt = id - g * Q3;
+                const int a = pt % Q, b = (pt / Q) % Q, c = pt / Q2;
+                const int ls = g * L::BUF + a + L::PITCH * b + L::PLANE * c;
+                const T *gm = qv[k];
+                const T ur = A[ls], us = C[ls], ut = Bb[ls];
+                A[ls] = gm[0] * ur + gm[5] * us + gm[4] * ut;
+                C[ls] = gm[5] * ur + gm[1] * us + gm[3] * ut;
+                Bb[ls] = gm[4] * ur + gm[3] * us + gm[2] * ut;
+            }
+        }
+        group_sync<NT>();
+        gf_xt<P, Q, G, NT, T>(A, Bb, C, bas, tid);
+        group_sync<NT>();
+        gf_yt<P, Q, G, NT, T>(A, Bb, C, bas, tid);
+        group_sync<NT>();
+        gf_zt<P, Q, G, NT, T>(A, Bb, bas, tid);
+        group_sync<NT>();
+        scatter_add<P, Q, G, NT, 1, T>(A, off, y, nvec, v0, nvalid, tid, ebuf, e0);
+        group_sync<NT>();
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Host launchers for one (P, Q) pair.
 // ---------------------------------------------------------------------------
 template <typename K>
@@ -859,7 +1259,7 @@ static hipError_t launch_apply_v(const ApplyLaunch &a)
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL(kern, dim3((unsigned)nblk), dim3(NT), lds, a.stream, static_cast<const T *>(a.basis_dev),
                            a.v.nex, ngroups, a.nvec, chain, a.v.offsets, static_cast<const T *>(a.v.qdata),
-                           static_cast<const T *>(a.x), static_cast<T *>(a.y));
+                           static_cast<const T *>(a.x), static_cast<T *>(a.y), static_cast<T *>(a.ebuf));
         return hipGetLastError();
     } else {
         const int64_t nblk = (int64_t)a.v.ney * a.v.nez * ((a.v.nex + G - 1) / G);
@@ -868,8 +1268,37 @@ static hipError_t launch_apply_v(const ApplyLaunch &a)
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL(kern, dim3((unsigned)nblk), dim3(NT), lds, a.stream, static_cast<const T *>(a.basis_dev),
                            a.v.nex, a.v.ney, a.nvec, a.v.offsets, static_cast<const T *>(a.v.qdata), a.v.kappa,
-                           a.wdet, a.vert, static_cast<const T *>(a.x), static_cast<T *>(a.y));
+                           a.wdet, a.vert, static_cast<const T *>(a.x), static_cast<T *>(a.y),
+                           static_cast<T *>(a.ebuf));
         return hipGetLastError();
+    }
+}
+
+template <int P, int Q, bool COLLOC, int MODE, bool VARK, typename T, int V, bool OTF = false>
+static hipError_t launch_apply_gfv(const ApplyLaunch &a)
+{
+    // the factored-gradient kernel: diffusion with Gauss points (not collocated), stored factors
+    if constexpr (MODE != kDiff || COLLOC || OTF) {
+        (void)a;
+        return hipErrorInvalidValue;
+    } else {
+        constexpr int G = variant_g(Q, V, MODE), NT = variant_nt(Q, V);
+        constexpr bool PF = gf_prefetch(V);
+        constexpr size_t lds = apply_lds(Q, MODE, sizeof(T), V, OTF);
+        if constexpr (lds > kMaxLds) {
+            (void)a;
+            return hipErrorInvalidValue;
+        } else {
+            const int64_t nblk = (int64_t)a.v.ney * a.v.nez * ((a.v.nex + G - 1) / G);
+            auto kern = k_apply_gf<P, Q, VARK, T, G, NT, PF>;
+            const hipError_t e = prepare_lds(kern, lds);
+            if (e != hipSuccess) return e;
+            hipLaunchKernelGGL(kern, dim3((unsigned)nblk), dim3(NT), lds, a.stream,
+                               static_cast<const T *>(a.basis_dev), a.v.nex, a.nvec, a.v.offsets,
+                               static_cast<const T *>(a.v.qdata), a.v.kappa, static_cast<const T *>(a.x),
+                               static_cast<T *>(a.y), static_cast<T *>(a.ebuf));
+            return hipGetLastError();
+        }
     }
 }
 
@@ -877,6 +1306,12 @@ template <int P, int Q, bool COLLOC, int MODE, bool VARK, typename T, bool OTF =
 static hipError_t launch_apply_t(const ApplyLaunch &a)
 {
     switch (a.variant) {
+    case 9: return launch_apply_gfv<P, Q, COLLOC, MODE, VARK, T, 9, OTF>(a);
+    case 10: return launch_apply_gfv<P, Q, COLLOC, MODE, VARK, T, 10, OTF>(a);
+    case 11: return launch_apply_gfv<P, Q, COLLOC, MODE, VARK, T, 11, OTF>(a);
+    case 12: return launch_apply_gfv<P, Q, COLLOC, MODE, VARK, T, 12, OTF>(a);
+    case 13: return launch_apply_gfv<P, Q, COLLOC, MODE, VARK, T, 13, OTF>(a);
+    case 14: return launch_apply_gfv<P, Q, COLLOC, MODE, VARK, T, 14, OTF>(a);
     case 8: return launch_apply_v<P, Q, COLLOC, MODE, VARK, T, 8, OTF>(a);
     case 0: return launch_apply_v<P, Q, COLLOC, MODE, VARK, T, 0, OTF>(a);
     case 1: return launch_apply_v<P, Q, COLLOC, MODE, VARK, T, 1, OTF>(a);

@@ -38,7 +38,8 @@ int validate(const mfhex_desc *d, Basis1D *basis)
     if (d->variable_kappa != 0 && d->variable_kappa != 1) return fail(MFHEX_ERR_ARG, "variable_kappa must be 0 or 1");
     if (d->variable_kappa && d->kind != MFHEX_DIFFUSION)
         return fail(MFHEX_ERR_ARG, "a variable coefficient needs a diffusion operator");
-    if (d->flags & ~(MFHEX_FLAG_F32 | MFHEX_FLAG_RHS | MFHEX_FLAG_OTF)) return fail(MFHEX_ERR_ARG, "unknown flag bits");
+    if (d->flags & ~(MFHEX_FLAG_F32 | MFHEX_FLAG_RHS | MFHEX_FLAG_OTF | MFHEX_FLAG_DETERMINISTIC))
+        return fail(MFHEX_ERR_ARG, "unknown flag bits");
     if ((d->flags & MFHEX_FLAG_OTF) &&
         (d->kind != MFHEX_DIFFUSION || d->variable_kappa || (d->flags & MFHEX_FLAG_F32)))
         return fail(MFHEX_ERR_UNSUPPORTED, "in-kernel geometric factors: FP64 diffusion with constant kappa only");
@@ -91,6 +92,11 @@ Layout workspace_layout(const mfhex_desc &d, int64_t E, int P, int Q)
     if ((d.flags & MFHEX_FLAG_RHS) && d.kind == MFHEX_DIFFUSION) {
         L.wdet = o;
         o += al(E * Q3 * sizeof(double));
+    }
+    L.ebuf = SIZE_MAX;
+    if (d.flags & MFHEX_FLAG_DETERMINISTIC) {
+        L.ebuf = o;
+        o += al(E * P3 * d.ncomp * sizeof(double));
     }
     L.basis = o;
     o += al(basis_len(P, Q) * (sizeof(double) + sizeof(float)) + 256);
@@ -155,6 +161,8 @@ bool valid_variant(const mfhex_op_s &op, int prec, int variant)
     if (variant_vc(variant) > 1 && op.d.variable_kappa) return false;
     const bool otf = (op.d.flags & MFHEX_FLAG_OTF) != 0;
     if (otf && variant_vc(variant) > 1) return false;  // in-kernel factors: single-vector variants
+    // the factored-gradient kernel: diffusion with Gauss points and stored factors
+    if (variant_gf(variant) && (mode_of(op) != kDiff || op.basis.colloc || otf)) return false;
     return apply_lds(op.Q, mode_of(op), prec == MFHEX_F32 ? 4 : 8, variant, otf) <= kMaxLds;
 }
 
@@ -169,7 +177,7 @@ int default_variant(const mfhex_op_s &op, int prec, int nvec)
                                            : kDefVariantDiff)[op.Q - 2];
         return valid_variant(op, prec, v) ? v : 0;
     }
-    for (int v = kNumVariants - 1; v >= 5; --v)
+    for (int v = 8; v >= 5; --v)  // the multi-vector chunk variants
         if (variant_vc(v) <= nvec && valid_variant(op, prec, v)) return v;
     return 0;
 }
@@ -264,13 +272,15 @@ int apply_impl(mfhex_op op, int prec, int nrhs, const void *x, void *y, hipStrea
     const size_t bytes = (size_t)op->N * nvec * (prec == MFHEX_F32 ? 4 : 8);
     const uintptr_t xa = (uintptr_t)x, ya = (uintptr_t)y;
     if (xa < ya + bytes && ya < xa + bytes) return set_error(op, MFHEX_ERR_ARG, "x and y overlap");
+    if (op->ebuf && nrhs != 1)
+        return set_error(op, MFHEX_ERR_UNSUPPORTED, "deterministic operators apply one right-hand side at a time");
     const LaunchCfg cfg = config_for(*op, prec, nvec);
     const int var = variant >= 0 ? variant : cfg.variant;
     if (!valid_variant(*op, prec, var)) return set_error(op, MFHEX_ERR_ARG, "invalid launch variant");
     const int nchain = chain > 0 ? chain : cfg.chain;
     if (nchain > kMaxChain || (nchain > 1 && mode_of(*op) != kMass))
         return set_error(op, MFHEX_ERR_ARG, "invalid pipeline depth");
-    if (zero) {
+    if (zero && !op->ebuf) {
         const int c = check_hip(op, launch_zero(y, bytes, s), "zero fill");
         if (c) return c;
     }
@@ -290,8 +300,14 @@ int apply_impl(mfhex_op op, int prec, int nrhs, const void *x, void *y, hipStrea
     a.x = x;
     a.y = y;
     a.wdet = nullptr;
+    a.ebuf = op->ebuf;
     a.stream = s;
-    return check_hip(op, launch_apply(a), "apply kernel launch");
+    const int c = check_hip(op, launch_apply(a), "apply kernel launch");
+    if (c || !op->ebuf) return c;
+    // deterministic operators: element values in the element buffer, summed per node in a fixed order
+    GeomLaunch g{op->d.nex, op->d.ney, op->d.nez, op->d.p, op->d.q, op->vert, &op->basis, s};
+    return check_hip(op, launch_det_assemble(g, op->d.dirichlet, nvec, prec, op->ebuf, y, !zero),
+                     "assembly kernel launch");
 }
 
 int diagonal_impl(mfhex_op op, double *d, hipStream_t s)
@@ -365,6 +381,7 @@ int mfhex_create(const mfhex_desc *d, void *workspace_dev, size_t workspace_byte
     op->q32 = L.q32 == SIZE_MAX ? nullptr : reinterpret_cast<float *>(ws + L.q32);
     op->kappa = L.kappa == SIZE_MAX ? nullptr : reinterpret_cast<double *>(ws + L.kappa);
     op->wdet = L.wdet == SIZE_MAX ? nullptr : reinterpret_cast<double *>(ws + L.wdet);
+    op->ebuf = L.ebuf == SIZE_MAX ? nullptr : static_cast<void *>(ws + L.ebuf);
     op->bad = reinterpret_cast<int32_t *>(ws + L.bad);
     op->basis64 = reinterpret_cast<double *>(ws + L.basis);
     op->basis32 = reinterpret_cast<float *>(ws + L.basis + ((basis_len(op->P, op->Q) * sizeof(double) + 255) & ~size_t(255)));
@@ -417,6 +434,14 @@ int mfhex_create(const mfhex_desc *d, void *workspace_dev, size_t workspace_byte
         for (int a = 0; a < Q; ++a) {
             h[basis_xq(P, Q) + a] = b.xq[a];
             h[basis_wq(P, Q) + a] = b.wq[a];
+        }
+        {
+            // the basis derivative at the points, G[a][i] = l_i'(x_a), and its transpose, folded
+            std::vector<double> g(Q * P), gt(P * Q);
+            for (int a = 0; a < Q; ++a)
+                for (int i = 0; i < P; ++i) g[a * P + i] = gt[i * Q + a] = b.Gn[a * P + i];
+            fold(g.data(), Q, P, &h[basis_gf(P, Q)]);
+            fold(gt.data(), P, Q, &h[basis_gtf(P, Q)]);
         }
         for (size_t i = 0; i < h.size(); ++i) h32[i] = (float)h[i];
         if ((c = check_hip(op, hipMemcpy(op->basis64, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice),

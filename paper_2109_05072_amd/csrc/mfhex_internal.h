@@ -69,6 +69,7 @@ struct ApplyLaunch {
     const void *x;        // input (for kRhs: the per-point f, FP64)
     void *y;              // output (accumulated)
     const double *wdet;   // kRhs: w*detJ per point
+    void *ebuf;           // deterministic scatter: element values [E][P^3][nvec] (null: atomics into y)
     hipStream_t stream;
 };
 
@@ -115,7 +116,7 @@ constexpr bool split_stages(int Q, int mode, int G, int NT, int VC)
 // 5..8 carry a chunk of VC = 2, 4, 8, 16 vectors of a multi-vector together
 // (one element per group), sharing the geometric factors and reading /
 // writing each node's chunk as one contiguous run.
-constexpr int kNumVariants = 9;
+constexpr int kNumVariants = 15;
 constexpr int kVarG[9][5] = {
     {16, 8, 32, 16, 32}, {8, 4, 16, 8, 16}, {4, 2, 8, 4, 8}, {4, 2, 8, 2, 8}, {1, 2, 1, 2, 4},
     {1, 2, 1, 1, 2},     {1, 1, 1, 2, 2},   {2, 1, 1, 1, 2}, {1, 1, 1, 2, 2}};
@@ -123,18 +124,33 @@ constexpr int kVarNT[9][5] = {
     {64, 64, 64, 128, 128},  {64, 64, 64, 128, 128},  {64, 64, 64, 128, 128},
     {128, 64, 128, 128, 256}, {64, 64, 128, 128, 128}, {64, 128, 128, 256, 64},
     {128, 256, 64, 128, 64}, {256, 128, 64, 256, 256}, {256, 128, 64, 128, 256}};
-constexpr int variant_vc(int v) { return v < 5 ? 1 : v == 5 ? 2 : v == 6 ? 4 : v == 7 ? 8 : 16; }
+constexpr int variant_vc(int v) { return v < 5 || v >= 9 ? 1 : v == 5 ? 2 : v == 6 ? 4 : v == 7 ? 8 : 16; }
+// Variants 9 .. 14: the factored-gradient diffusion kernel (Gauss points, one vector at a time;
+// k_apply_gf): 9 .. 13 take the (elements, threads) pairs below per q and load the geometric
+// factors at the start of the element group; 14 is variant 9 loading them in the middle of the
+// forward stages (fewer registers held through the first contractions).
+constexpr int kGfG[9][5] = {{16, 8, 32, 16, 8}, {16, 8, 32, 16, 8}, {8, 4, 16, 8, 4}, {8, 4, 2, 8, 4},
+                            {4, 2, 8, 4, 2},    {2, 1, 4, 2, 1},    {1, 2, 4, 1, 2}, {1, 1, 2, 2, 1},
+                            {1, 1, 2, 2, 1}};
+constexpr int kGfNT[9][5] = {{128, 64, 256, 256, 128}, {128, 64, 256, 256, 128}, {128, 64, 256, 256, 128},
+                             {256, 128, 64, 128, 64},  {128, 64, 256, 256, 128}, {128, 64, 256, 64, 128},
+                             {64, 128, 256, 128, 64},  {128, 64, 256, 128, 256}, {128, 64, 256, 128, 256}};
+constexpr bool variant_gf(int v) { return v >= 9; }
+constexpr bool gf_prefetch(int v) { return v != 14; }
+constexpr int gf_slot(int v) { return v == 14 ? 0 : v - 9; }
 // The mass operator keeps one LDS array per element instead of three and has
 // far less work per element, so at low order its single-vector variants
 // carry more elements per group.
 constexpr int mass_group_scale(int Q) { return Q <= 4 ? 4 : Q <= 6 ? 2 : 1; }
 constexpr int variant_g(int Q, int v, int mode = 1)
 {
-    return v < 5 ? kVarG[Q - 2][v] * (mode == 1 ? 1 : mass_group_scale(Q)) : 1;
+    return variant_gf(v) ? kGfG[Q - 2][gf_slot(v)] : v < 5 ? kVarG[Q - 2][v] * (mode == 1 ? 1 : mass_group_scale(Q)) : 1;
 }
 constexpr int variant_nt(int Q, int v)
 {
-    return v < 5 ? kVarNT[Q - 2][v] : (Q * Q * variant_vc(v) <= 64 ? 64 : Q * Q * variant_vc(v) <= 128 ? 128 : 256);
+    return variant_gf(v) ? kGfNT[Q - 2][gf_slot(v)]
+           : v < 5       ? kVarNT[Q - 2][v]
+                         : (Q * Q * variant_vc(v) <= 64 ? 64 : Q * Q * variant_vc(v) <= 128 ? 128 : 256);
 }
 // Dynamic LDS bytes of one group of the fused apply.
 // In-kernel geometric factors: per element its 8 vertices (24 doubles) and
@@ -143,7 +159,7 @@ constexpr int otf_lds_doubles(int Q, int G) { return G * (24 + 9 * Q * Q) + 2 * 
 
 constexpr bool variant_split(int Q, int v, int mode)
 {
-    return split_stages(Q, mode, variant_g(Q, v, mode), variant_nt(Q, v), variant_vc(v));
+    return !variant_gf(v) && split_stages(Q, mode, variant_g(Q, v, mode), variant_nt(Q, v), variant_vc(v));
 }
 constexpr size_t apply_lds(int Q, int mode, int elem_bytes, int v, bool otf = false)
 {
@@ -183,7 +199,10 @@ constexpr int basis_df(int P, int Q) { return basis_btf(P, Q) + half_up(P) * Q; 
 constexpr int basis_dtf(int P, int Q) { return basis_df(P, Q) + half_up(Q) * Q; }
 constexpr int basis_xq(int P, int Q) { return basis_dtf(P, Q) + half_up(Q) * Q; }  // quadrature points [Q]
 constexpr int basis_wq(int P, int Q) { return basis_xq(P, Q) + Q; }                  // quadrature weights [Q]
-constexpr int basis_len(int P, int Q) { return basis_wq(P, Q) + Q; }
+// folded G [Q][P] (G[a][i] = l_i'(x_a), the basis derivative at the points) and folded G^T [P][Q]
+constexpr int basis_gf(int P, int Q) { return basis_wq(P, Q) + Q; }
+constexpr int basis_gtf(int P, int Q) { return basis_gf(P, Q) + half_up(Q) * P; }
+constexpr int basis_len(int P, int Q) { return basis_gtf(P, Q) + half_up(P) * Q; }
 
 // Per-order dispatch (one translation unit per order, apply_p<N>.hip).
 hipError_t launch_apply(const ApplyLaunch &a);
@@ -214,6 +233,11 @@ struct GeomLaunch {
 // mass -> w detJ.  q32 (optional) gets the FP32 rounding, wdet (optional) w detJ.
 // bad gets a nonzero value if some detJ <= 0 (caller zeroes it first).
 hipError_t launch_qdata(const GeomLaunch &g, int kind, double *q64, float *q32, double *wdet, int32_t *bad);
+// Deterministic transposed restriction: y[n][v] (+)= sum of the element values ebuf[e][local][v] of
+// the (up to 8) elements holding node n, in increasing element order; masked nodes keep y (add) or
+// get 0.  prec: MFHEX_F64 / MFHEX_F32.
+hipError_t launch_det_assemble(const GeomLaunch &g, int dirichlet, int nvec, int prec, const void *ebuf, void *y,
+                               bool add);
 hipError_t launch_offsets(const GeomLaunch &g, int dirichlet, int32_t *off);
 hipError_t launch_qpoint_coords(const GeomLaunch &g, double *xyz);
 hipError_t launch_node_coords(const GeomLaunch &g, double *xyz);

@@ -22,6 +22,7 @@ struct mfhex_op_s {
     float *q32 = nullptr;
     double *kappa = nullptr;
     double *wdet = nullptr;
+    void *ebuf = nullptr;       // deterministic operators: element values [E][P^3][ncomp]
     int32_t *bad = nullptr;
     double *basis64 = nullptr;  // device basis block, FP64 and FP32
     float *basis32 = nullptr;
@@ -36,7 +37,7 @@ namespace mfhex {
 
 // Workspace layout (byte offsets, 256-aligned); absent parts are SIZE_MAX.
 struct Layout {
-    size_t vert, offsets, q64, q32, kappa, wdet, basis, bad, total;
+    size_t vert, offsets, q64, q32, kappa, wdet, ebuf, basis, bad, total;
 };
 Layout workspace_layout(const mfhex_desc &d, int64_t E, int P, int Q);
 

@@ -105,6 +105,49 @@ __global__ void k_offsets(int32_t nex, int32_t ney, int32_t nez, int p, int diri
     off[gid] = (dirichlet && bnd) ? -1 : (int32_t)(I + (lx + 1) * (J + (ly + 1) * K));
 }
 
+// Deterministic transposed restriction: node n = (I, J, K) lies in the elements
+// ex in {I/p - 1 (when I is a multiple of p and > 0), I/p (when < nex)}, and
+// likewise in y and z, at local index I - p ex; their values are summed in
+// increasing element order (z, then y, then x), so the result does not depend
+// on the order in which the elements were computed.  One thread per (node,
+// vector) pair.
+template <typename T>
+__global__ void k_det_assemble(int32_t nex, int32_t ney, int32_t nez, int p, int dirichlet, int nvec,
+                               const T *__restrict__ ebuf, T *__restrict__ y, int add)
+{
+    const int64_t lx = (int64_t)p * nex, ly = (int64_t)p * ney, lz = (int64_t)p * nez;
+    const int64_t nn = (lx + 1) * (ly + 1) * (lz + 1);
+    const int64_t gid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (gid >= nn * nvec) return;
+    const int64_t n = gid / nvec;
+    const int v = (int)(gid - n * nvec);
+    const int64_t I = n % (lx + 1), J = (n / (lx + 1)) % (ly + 1), K = n / ((lx + 1) * (ly + 1));
+    const bool bnd = I == 0 || I == lx || J == 0 || J == ly || K == 0 || K == lz;
+    if (dirichlet && bnd) {
+        if (!add) y[gid] = T(0);
+        return;
+    }
+    const int P = p + 1, P3 = P * P * P;
+    // candidate element coordinates per direction, ascending: (I - 1)/p when I is an inner multiple of p, then I/p
+    auto cand = [p](int64_t I, int64_t ne, int64_t c[2]) {
+        int m = 0;
+        if (I % p == 0 && I > 0) c[m++] = I / p - 1;
+        if (I / p < ne) c[m++] = I / p;
+        return m;
+    };
+    int64_t cx[2], cy[2], cz[2];
+    const int mx = cand(I, nex, cx), my = cand(J, ney, cy), mz = cand(K, nez, cz);
+    T sum = T(0);
+    for (int a = 0; a < mz; ++a)
+        for (int b = 0; b < my; ++b)
+            for (int c = 0; c < mx; ++c) {
+                const int64_t e = cx[c] + nex * (cy[b] + (int64_t)ney * cz[a]);
+                const int loc = (int)(I - p * cx[c]) + P * ((int)(J - p * cy[b]) + P * (int)(K - p * cz[a]));
+                sum += ebuf[(e * P3 + loc) * nvec + v];
+            }
+    y[gid] = add ? y[gid] + sum : sum;
+}
+
 Rule1D quad_rule(const Basis1D &b)
 {
     Rule1D r{};
@@ -133,6 +176,20 @@ hipError_t launch_offsets(const GeomLaunch &g, int dirichlet, int32_t *off)
     const int64_t n = (int64_t)g.nex * g.ney * g.nez * P * P * P;
     hipLaunchKernelGGL(k_offsets, dim3(nblocks(n, 256)), dim3(256), 0, g.stream, g.nex, g.ney, g.nez, g.p, dirichlet,
                        off);
+    return hipGetLastError();
+}
+
+hipError_t launch_det_assemble(const GeomLaunch &g, int dirichlet, int nvec, int prec, const void *ebuf, void *y,
+                               bool add)
+{
+    const int64_t n = (int64_t)(g.p * g.nex + 1) * (g.p * g.ney + 1) * (g.p * g.nez + 1) * nvec;
+    if (prec == MFHEX_F32)
+        hipLaunchKernelGGL(k_det_assemble<float>, dim3(nblocks(n, 256)), dim3(256), 0, g.stream, g.nex, g.ney, g.nez,
+                           g.p, dirichlet, nvec, static_cast<const float *>(ebuf), static_cast<float *>(y), (int)add);
+    else
+        hipLaunchKernelGGL(k_det_assemble<double>, dim3(nblocks(n, 256)), dim3(256), 0, g.stream, g.nex, g.ney,
+                           g.nez, g.p, dirichlet, nvec, static_cast<const double *>(ebuf), static_cast<double *>(y),
+                           (int)add);
     return hipGetLastError();
 }
 

@@ -52,18 +52,22 @@ class Operator:
     ``quad``: "gauss" (q = p+2) or "gll" (q = p+1, collocated).
     ``otf``: diffusion in FP64 with the geometric factors evaluated in the kernel from the element
     vertices instead of stored (no factor array in the workspace).
+    ``deterministic``: atomic-free scatter (element values stored, then summed per node in a fixed
+    order), one right-hand side per apply.
     """
 
     def __init__(self, nex: int, ney: int, nez: int, p: int, vertices: np.ndarray, kind: str = "diffusion",
                  quad: str = "gauss", ncomp: int = 1, dirichlet: bool = True, variable_kappa: bool = False,
-                 f32: bool = False, rhs: bool = False, otf: bool = False, device: str = "cuda"):
+                 f32: bool = False, rhs: bool = False, otf: bool = False, deterministic: bool = False,
+                 device: str = "cuda"):
         L.load()
         if not torch.cuda.is_available():
             raise RuntimeError("no GPU: the matrix-free operators run only on the HIP device")
         self.device = torch.device(device)
         q = p + 2 if quad == "gauss" else p + 1
         self._vert = np.ascontiguousarray(vertices, dtype=np.float64)
-        flags = (L.MFHEX_FLAG_F32 if f32 else 0) | (L.MFHEX_FLAG_RHS if rhs else 0) | (L.MFHEX_FLAG_OTF if otf else 0)
+        flags = ((L.MFHEX_FLAG_F32 if f32 else 0) | (L.MFHEX_FLAG_RHS if rhs else 0) | (L.MFHEX_FLAG_OTF if otf else 0)
+                 | (L.MFHEX_FLAG_DETERMINISTIC if deterministic else 0))
         self.desc = L.mfhex_desc(nex, ney, nez, p, q, _QUADS[quad], _KINDS[kind], ncomp, int(dirichlet),
                                  int(variable_kappa), flags, self._vert.ctypes.data_as(C.POINTER(C.c_double)))
         self.sizes = L.mfhex_query(self.desc)

@@ -54,6 +54,7 @@ def test_query_sizes():
     h = lambda n: (n + 1) // 2  # noqa: E731
     # plain B, B^T, D, D^T and their folded (even-odd) half-row forms
     nb = 2 * Q * P + 2 * Q * Q + h(Q) * P + h(P) * Q + 2 * h(Q) * Q + 2 * Q  # ... and the 1D rule (x, w)
+    nb += h(Q) * P + h(P) * Q  # folded basis derivative at the points and its transpose
     expect = (al(4 * 3 * 5 * 3 * 8) + al(24 * 27 * 4) + al(24 * 6 * 64 * 8) + al(24 * 6 * 64 * 4)
               + al(nb * 12 + 256) + 256)
     assert s.workspace_bytes == expect
@@ -61,6 +62,9 @@ def test_query_sizes():
     # in-kernel geometric factors: the same layout without either factor array
     d2 = _desc(3, 2, 4, p=2, flags=L.MFHEX_FLAG_OTF)
     assert L.mfhex_query(d2).workspace_bytes == expect - al(24 * 6 * 64 * 8) - al(24 * 6 * 64 * 4)
+    # deterministic scatter: the same layout plus the element-value buffer [E][P^3][ncomp] in FP64
+    d3 = _desc(3, 2, 4, p=2, ncomp=3, flags=L.MFHEX_FLAG_F32 | L.MFHEX_FLAG_DETERMINISTIC)
+    assert L.mfhex_query(d3).workspace_bytes == expect + al(24 * 27 * 3 * 8)
 
 
 @pytest.mark.parametrize("kw,code", [
@@ -72,7 +76,7 @@ def test_query_sizes():
     (dict(quad=L.MFHEX_GAUSS, q=4, p=3), L.MFHEX_ERR_UNSUPPORTED),
     (dict(kind=3), L.MFHEX_ERR_ARG),
     (dict(kind=L.MFHEX_MASS, vark=1), L.MFHEX_ERR_ARG),
-    (dict(flags=8), L.MFHEX_ERR_ARG),
+    (dict(flags=16), L.MFHEX_ERR_ARG),
     (dict(flags=L.MFHEX_FLAG_OTF, kind=L.MFHEX_MASS, dirichlet=0), L.MFHEX_ERR_UNSUPPORTED),
     (dict(flags=L.MFHEX_FLAG_OTF | L.MFHEX_FLAG_F32), L.MFHEX_ERR_UNSUPPORTED),
     (dict(flags=L.MFHEX_FLAG_OTF, vark=1), L.MFHEX_ERR_UNSUPPORTED),

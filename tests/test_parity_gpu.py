@@ -30,10 +30,10 @@ def relerr(a, b):
 
 
 def build(mf, nex, ney, nez, p, kind="diffusion", quad="gauss", dirichlet=True, ncomp=1, vark=False, f32=False,
-          rhs=False, perturb=0.1, otf=False):
+          rhs=False, perturb=0.1, otf=False, det=False):
     vert = synth.mesh_vertices(nex, ney, nez, perturb)
     op = mf.Operator(nex, ney, nez, p, vert, kind=kind, quad=quad, ncomp=ncomp, dirichlet=dirichlet,
-                     variable_kappa=vark, f32=f32, rhs=rhs, otf=otf)
+                     variable_kappa=vark, f32=f32, rhs=rhs, otf=otf, deterministic=det)
     q = p + 2 if quad == "gauss" else p + 1
     pr = oracle.Problem(nex, ney, nez, p, q, oracle.GAUSS if quad == "gauss" else oracle.GLL,
                         oracle.DIFFUSION if kind == "diffusion" else oracle.MASS, int(dirichlet), vert)
@@ -60,7 +60,7 @@ def valid_variants(op, dtype=torch.float64, nrhs=1):
     """Launch variants the operator accepts (some exceed the LDS budget at high order)."""
     from paper_2109_05072_amd import _lib as L
     out = []
-    for v in range(9):
+    for v in range(15):
         try:
             op.set_config(v, dtype, nrhs)
             out.append(v)
@@ -258,6 +258,58 @@ def test_run_to_run_spread(gpu_lib):
     spread = max(relerr(y, ys[0]) for y in ys)
     print("run-to-run spread", spread)
     assert spread <= 1e-14
+
+
+# --- deterministic (atomic-free) scatter: the reference for the atomic path ---------------------
+
+@pytest.mark.parametrize("p", [1, 2, 3, 5, 7, 8])
+@pytest.mark.parametrize("kind,quad,ncomp", [("diffusion", "gauss", 1), ("diffusion", "gll", 3), ("mass", "gauss", 1)])
+def test_deterministic_scatter_matches_atomic_and_oracle(gpu_lib, p, kind, quad, ncomp):
+    _say("det", p, kind, quad, ncomp)
+    dirichlet = kind == "diffusion"
+    op, pr = build(gpu_lib, 5, 3, 2, p, kind, quad, dirichlet, ncomp=ncomp, f32=True, det=True)
+    ref, _ = build(gpu_lib, 5, 3, 2, p, kind, quad, dirichlet, ncomp=ncomp, f32=True)
+    x = synth.uniform_vector(pr.n_nodes, nvec=ncomp) if ncomp > 1 else synth.uniform_vector(pr.n_nodes)
+    yo = oracle.apply(pr, x)
+    for v in valid_variants(op):
+        op.set_config(v)
+        ref.set_config(v)
+        _say("det variant", v, op.get_config())
+        yd = host(op.apply(dev(x)))
+        assert relerr(yd, yo) <= TOL64
+        assert relerr(yd, host(ref.apply(dev(x)))) <= 1e-14
+        if dirichlet:
+            assert np.all(yd.reshape(pr.n_nodes, -1)[interior_mask(pr) == 0] == 0.0)
+    # FP32 and y += A x
+    y32 = host(op.apply(dev(x, torch.float32)))
+    assert relerr(y32, yo) <= TOL32
+    y0 = synth.uniform_vector(pr.n_nodes * ncomp, seed=8).reshape(x.shape)
+    yt = dev(y0)
+    op.apply_add(dev(x), yt)
+    assert relerr(host(yt), y0 + yo) <= TOL64
+    # one right-hand side per apply
+    from paper_2109_05072_amd import _lib as L
+    with pytest.raises(L.MFHexError) as ei:
+        op.apply(dev(np.stack([x, x], axis=1) if ncomp == 1 else np.concatenate([x, x], axis=1)))
+    assert ei.value.code == L.MFHEX_ERR_UNSUPPORTED
+
+
+def test_deterministic_scatter_is_bitwise_reproducible(gpu_lib):
+    # the atomic path differs from run to run in the last bits; the deterministic path not at all, and
+    # agrees with the atomic path to rounding (about 2.6e5 nodes, several hundred element groups per XCD)
+    op, pr = build(gpu_lib, 21, 21, 21, 3, det=True)
+    ref, _ = build(gpu_lib, 21, 21, 21, 3)
+    x = dev(synth.uniform_vector(pr.n_nodes))
+    yd = [host(op.apply(x)) for _ in range(4)]
+    ya = [host(ref.apply(x)) for _ in range(4)]
+    print("det runs identical:", all(np.array_equal(y, yd[0]) for y in yd),
+          "atomic spread", max(relerr(y, ya[0]) for y in ya), "det vs atomic", relerr(yd[0], ya[0]))
+    assert all(np.array_equal(y, yd[0]) for y in yd)
+    assert relerr(yd[0], ya[0]) <= 1e-14
+    # CG on the deterministic operator: the whole residual history repeats exactly
+    b = dev(synth.uniform_vector(pr.n_nodes, seed=3) * interior_mask(pr))
+    h = [op.cg(b, maxit=40, rtol=0.0, exact_iters=True).history for _ in range(2)]
+    assert np.array_equal(h[0], h[1])
 
 
 # --- autotuner ------------------------------------------------------------------------------
