@@ -200,8 +200,9 @@ def main():
     if args.kind == "diffusion":
         tag = "otf " if args.otf else ""
         traffic = read_traffic(os.path.join(ROOT, "profiles", f"bp3{'_otf' if args.otf else ''}_apply_traffic.txt"))
-        dom_name = (f"k_apply p={dom['p']} q={dom['p'] + 2} diffusion {tag}double G={lg['elements_per_group']} "
-                    f"NT={lg['threads_per_group']}")
+        kname = "k_apply_gf" if lg["variant"] >= 9 else "k_apply"
+        dom_name = (f"{kname} p={dom['p']} q={dom['p'] + 2} diffusion {tag}double G={lg['elements_per_group']} "
+                    f"NT={lg['threads_per_group']}{' late-factors' if lg['variant'] == 14 else ''}")
     else:
         traffic = read_traffic(os.path.join(ROOT, "profiles", "bp1_apply_traffic.txt"))
         dom_name = (f"k_mass p={dom['p']} q={dom['p'] + 2} double G={lg['elements_per_group']} "

@@ -47,6 +47,11 @@ def _short(name: str) -> str:
         vc = f" VC={VC}" if VC and VC != "1" else ""
         geo = " otf" if otf == "true" else ""
         return f"k_apply p={int(P) - 1} q={Q} {kind}{' kappa' if vark == 'true' else ''}{geo} {T} G={G} NT={NT}{vc}"
+    m = re.match(r"void mfhex::k_apply_gf<(\d+), (\d+), (\w+), (\w+), (\d+), (\d+), (\w+)>", name)
+    if m:
+        P, Q, vark, T, G, NT, pf = m.groups()
+        late = "" if pf == "true" else " late-factors"
+        return f"k_apply_gf p={int(P) - 1} q={Q} diffusion{' kappa' if vark == 'true' else ''} {T} G={G} NT={NT}{late}"
     m = re.match(r"void mfhex::k_mass<(\d+), (\d+), (\w+), (\w+), (\d+), (\d+), (\d+)>", name)
     if m:
         P, Q, colloc, T, G, NT, VC = m.groups()

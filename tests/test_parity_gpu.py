@@ -326,7 +326,7 @@ def test_every_launch_configuration_agrees(gpu_lib, p, quad, nrhs):
         op.set_config(v, nrhs=nrhs)
         assert relerr(host(op.apply(x)), ref) <= 1e-13
     with pytest.raises(L.MFHexError):
-        op.set_config(9, nrhs=nrhs)
+        op.set_config(15, nrhs=nrhs)  # one past the last variant
     best = op.tune(nrhs=nrhs)
     assert best[0] in vs and best[3] == 1
     assert relerr(host(op.apply(x)), ref) <= 1e-13
