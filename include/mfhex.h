@@ -157,6 +157,26 @@ int mfhex_apply_add(mfhex_op op, int prec, int nrhs, const void *x_dev, void *y_
  * mfhex_apply. */
 int mfhex_apply_adjoint(mfhex_op op, int prec, int nrhs, const void *x_dev, void *y_dev, void *stream);
 
+/* For callers that cannot allocate device memory (code under stream capture,
+ * serving loops, harnesses that forbid hipMalloc): y = A x for one
+ * right-hand side (nvec = ncomp), in the deterministic form of
+ * MFHEX_FLAG_DETERMINISTIC (element values stored, then summed per node in
+ * increasing element order), on any operator, with or without that flag.
+ * The element values live in a device array the library owns: one copy per
+ * GPU, mfhex_apply_static_max_bytes() = 64 MiB, held until the process
+ * ends.  The operator needs n_elem (p+1)^3 ncomp values of that buffer (8
+ * bytes each for MFHEX_F64, 4 for MFHEX_F32); above the maximum the call
+ * returns MFHEX_ERR_ARG and launches nothing.  The operator's device must be
+ * current (MFHEX_ERR_STATE otherwise); the first call on a device looks up
+ * that device's copy of the array.  No allocation, no host synchronization:
+ * it enqueues the apply and assembly kernels on `stream`.  Every call on one
+ * GPU shares that GPU's array, so calls that overlap in time on one GPU
+ * (two streams, two host threads) race; calls ordered on one stream do not.
+ * x, y and prec as in mfhex_apply (y fully overwritten); the result equals
+ * mfhex_apply on an operator created with MFHEX_FLAG_DETERMINISTIC. */
+int mfhex_apply_static(mfhex_op op, int prec, const void *x_dev, void *y_dev, void *stream);
+size_t mfhex_apply_static_max_bytes(void);
+
 /* Gradient of s = r^T (M A(kappa) M) u with respect to the per-point
  * coefficient (the paper defines none; with A^e = D^T (kappa G0^e) D of
  * Sec. 2, s is linear in each kappa_pt, and its derivative is the pointwise

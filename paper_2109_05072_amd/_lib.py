@@ -31,7 +31,7 @@ MFHEX_FLAG_F32, MFHEX_FLAG_RHS, MFHEX_FLAG_OTF, MFHEX_FLAG_DETERMINISTIC = 1, 2,
 # every symbol include/mfhex.h declares
 EXPORTS = (
     "mfhex_query", "mfhex_create", "mfhex_destroy", "mfhex_set_kappa", "mfhex_apply", "mfhex_apply_add",
-    "mfhex_apply_adjoint", "mfhex_kappa_grad", "mfhex_qpoint_coords", "mfhex_node_coords", "mfhex_rhs",
+    "mfhex_apply_adjoint", "mfhex_apply_static", "mfhex_apply_static_max_bytes", "mfhex_kappa_grad", "mfhex_qpoint_coords", "mfhex_node_coords", "mfhex_rhs",
     "mfhex_cg", "mfhex_tune", "mfhex_get_config", "mfhex_set_config", "mfhex_diagonal", "mfhex_mg_query", "mfhex_mg_setup",
     "mfhex_mg_apply", "mfhex_mg_level", "mfhex_strerror", "mfhex_last_error",
     "mfhex_basis_1d", "mfhex_version",
@@ -113,6 +113,8 @@ def load(path: str = LIB_PATH):
         "mfhex_apply": ([vp, i32, i32, vp, vp, vp], i32),
         "mfhex_apply_add": ([vp, i32, i32, vp, vp, vp], i32),
         "mfhex_apply_adjoint": ([vp, i32, i32, vp, vp, vp], i32),
+        "mfhex_apply_static": ([vp, i32, vp, vp, vp], i32),
+        "mfhex_apply_static_max_bytes": ([], sz),
         "mfhex_kappa_grad": ([vp, vp, vp, vp, vp], i32),
         "mfhex_qpoint_coords": ([vp, vp, vp], i32),
         "mfhex_node_coords": ([vp, vp, vp], i32),
@@ -186,6 +188,14 @@ def mfhex_apply_add(op: int, prec: int, nrhs: int, x: int, y: int, stream: int) 
 
 def mfhex_apply_adjoint(op: int, prec: int, nrhs: int, x: int, y: int, stream: int) -> None:
     check(load().mfhex_apply_adjoint(op, prec, nrhs, x, y, stream), op)
+
+
+def mfhex_apply_static(op: int, prec: int, x: int, y: int, stream: int) -> None:
+    check(load().mfhex_apply_static(op, prec, x, y, stream), op)
+
+
+def mfhex_apply_static_max_bytes() -> int:
+    return int(load().mfhex_apply_static_max_bytes())
 
 
 def mfhex_kappa_grad(op: int, u: int, r: int, g: int, stream: int) -> None:

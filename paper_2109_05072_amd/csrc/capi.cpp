@@ -257,7 +257,8 @@ static OpView view_of(const mfhex_op_s &op, int prec)
     return v;
 }
 
-int apply_impl(mfhex_op op, int prec, int nrhs, const void *x, void *y, hipStream_t s, bool zero, int variant, int chain)
+int apply_impl(mfhex_op op, int prec, int nrhs, const void *x, void *y, hipStream_t s, bool zero, int variant, int chain,
+               void *ebuf_in)
 {
     if (!op) return set_error(nullptr, MFHEX_ERR_ARG, "null handle");
     if (prec != MFHEX_F64 && prec != MFHEX_F32) return set_error(op, MFHEX_ERR_ARG, "prec must be F64 or F32");
@@ -272,7 +273,8 @@ int apply_impl(mfhex_op op, int prec, int nrhs, const void *x, void *y, hipStrea
     const size_t bytes = (size_t)op->N * nvec * (prec == MFHEX_F32 ? 4 : 8);
     const uintptr_t xa = (uintptr_t)x, ya = (uintptr_t)y;
     if (xa < ya + bytes && ya < xa + bytes) return set_error(op, MFHEX_ERR_ARG, "x and y overlap");
-    if (op->ebuf && nrhs != 1)
+    void *const ebuf = ebuf_in ? ebuf_in : op->ebuf;
+    if (ebuf && nrhs != 1)
         return set_error(op, MFHEX_ERR_UNSUPPORTED, "deterministic operators apply one right-hand side at a time");
     const LaunchCfg cfg = config_for(*op, prec, nvec);
     const int var = variant >= 0 ? variant : cfg.variant;
@@ -280,7 +282,7 @@ int apply_impl(mfhex_op op, int prec, int nrhs, const void *x, void *y, hipStrea
     const int nchain = chain > 0 ? chain : cfg.chain;
     if (nchain > kMaxChain || (nchain > 1 && mode_of(*op) != kMass))
         return set_error(op, MFHEX_ERR_ARG, "invalid pipeline depth");
-    if (zero && !op->ebuf) {
+    if (zero && !ebuf) {
         const int c = check_hip(op, launch_zero(y, bytes, s), "zero fill");
         if (c) return c;
     }
@@ -300,13 +302,13 @@ int apply_impl(mfhex_op op, int prec, int nrhs, const void *x, void *y, hipStrea
     a.x = x;
     a.y = y;
     a.wdet = nullptr;
-    a.ebuf = op->ebuf;
+    a.ebuf = ebuf;
     a.stream = s;
     const int c = check_hip(op, launch_apply(a), "apply kernel launch");
-    if (c || !op->ebuf) return c;
+    if (c || !ebuf) return c;
     // deterministic operators: element values in the element buffer, summed per node in a fixed order
     GeomLaunch g{op->d.nex, op->d.ney, op->d.nez, op->d.p, op->d.q, op->vert, &op->basis, s};
-    return check_hip(op, launch_det_assemble(g, op->d.dirichlet, nvec, prec, op->ebuf, y, !zero),
+    return check_hip(op, launch_det_assemble(g, op->d.dirichlet, nvec, prec, ebuf, y, !zero),
                      "assembly kernel launch");
 }
 

@@ -57,8 +57,10 @@ int check_hip(mfhex_op op, hipError_t e, const char *what);
 
 // Internal apply: y (+)= A x on `s` with an explicit configuration.
 // variant < 0 / chain <= 0: the handle's configuration for (prec, nvec).
+// ebuf (optional): element-value buffer that makes this call deterministic (element values stored,
+// then summed per node in a fixed order), in place of the operator's own.
 int apply_impl(mfhex_op op, int prec, int nrhs, const void *x, void *y, hipStream_t s, bool zero, int variant = -1,
-               int chain = 0);
+               int chain = 0, void *ebuf = nullptr);
 int default_variant(const mfhex_op_s &op, int prec, int nvec);
 bool valid_variant(const mfhex_op_s &op, int prec, int variant);
 LaunchCfg config_for(const mfhex_op_s &op, int prec, int nvec);

@@ -154,6 +154,17 @@ class Operator:
         L.mfhex_apply_adjoint(self.handle, _prec(x.dtype), nrhs, x.data_ptr(), y.data_ptr(), _stream())
         return y
 
+    def apply_static(self, x: torch.Tensor, y: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """y = A x for one right-hand side in the deterministic summation order, with the element
+        values in the library's own device buffer (mfhex_apply_static: no allocation in the call)."""
+        nrhs = self._nrhs(x)
+        if nrhs != 1:
+            raise ValueError("apply_static takes one right-hand side")
+        y = torch.empty_like(x) if y is None else y
+        self._check_pair(x, y, 1)
+        L.mfhex_apply_static(self.handle, _prec(x.dtype), x.data_ptr(), y.data_ptr(), _stream())
+        return y
+
     def set_kappa(self, kappa: torch.Tensor) -> None:
         kappa = kappa.contiguous()
         self._check_vec(kappa, 1, dtype=torch.float64, name="kappa", n=self.n_elem * self.q ** 3)
