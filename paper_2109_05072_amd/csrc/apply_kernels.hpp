@@ -364,18 +364,19 @@ __device__ __forceinline__ void gather(T *s0, const int32_t (&off)[NR], const T 
 // values summed for a face shared inside the group) for unmasked nodes, with
 // hardware atomics (nodes on the group boundary are shared with other groups).
 //
-// Deterministic form (ebuf non-null): no atomics; every element stores its own
-// values at ebuf[(e P^3 + local node) nvec + vector] with plain stores (a face
-// node shared inside the group is stored once for each of its two elements),
-// and k_det_assemble later sums each node's element values in a fixed order.
-template <int P, int Q, int G, int NT, int VC, typename T, int NR>
+// Deterministic form (DET, a separate instantiation so that the atomic form
+// keeps its registers): no atomics; every element stores its own values at
+// ebuf[(e P^3 + local node) nvec + vector] with plain stores (a face node
+// shared inside the group is stored once for each of its two elements), and
+// k_det_assemble later sums each node's element values in a fixed order.
+template <int P, int Q, int G, int NT, int VC, bool DET, typename T, int NR>
 __device__ __forceinline__ void scatter_add(const T *s0, const int32_t (&off)[NR], T *__restrict__ y, int nvec, int v0,
-                                            int nvalid, int tid, T *__restrict__ ebuf = nullptr, int64_t e0 = 0)
+                                            int nvalid, int tid, T *__restrict__ ebuf, int64_t e0)
 {
     static_assert(NR == NodeIO<P, G, NT, VC>::NR, "offset count");
     using L = Lds<Q>;
     using IO = NodeIO<P, G, NT, VC>;
-    if (ebuf) {
+    if constexpr (DET) {
         constexpr int P3 = P * P * P;
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
@@ -393,20 +394,22 @@ __device__ __forceinline__ void scatter_add(const T *s0, const int32_t (&off)[NR
                         s0[((g - 1) * VC + vc) * L::BUF + (P - 1) + jk];
             }
         }
-        return;
-    }
+    } else {
+        (void)ebuf;
+        (void)e0;
 #pragma unroll
-    for (int r = 0; r < NR; ++r) {
-        const int id = tid + r * NT;
-        const int vc = id % VC;
-        if (off[r] >= 0 && v0 + vc < nvec) {
-            const int u = id / VC, line = u / IO::W, X = u - line * IO::W;
-            int g, i;
-            line_pos<P, G>(X, nvalid, g, i);
-            const int jk = L::PITCH * (line % P) + L::PLANE * (line / P);
-            T v = s0[(g * VC + vc) * L::BUF + i + jk];
-            if (G > 1 && i == 0 && g > 0) v += s0[((g - 1) * VC + vc) * L::BUF + (P - 1) + jk];
-            unsafeAtomicAdd(&y[(int64_t)off[r] * nvec + v0 + vc], v);
+        for (int r = 0; r < NR; ++r) {
+            const int id = tid + r * NT;
+            const int vc = id % VC;
+            if (off[r] >= 0 && v0 + vc < nvec) {
+                const int u = id / VC, line = u / IO::W, X = u - line * IO::W;
+                int g, i;
+                line_pos<P, G>(X, nvalid, g, i);
+                const int jk = L::PITCH * (line % P) + L::PLANE * (line / P);
+                T v = s0[(g * VC + vc) * L::BUF + i + jk];
+                if (G > 1 && i == 0 && g > 0) v += s0[((g - 1) * VC + vc) * L::BUF + (P - 1) + jk];
+                unsafeAtomicAdd(&y[(int64_t)off[r] * nvec + v0 + vc], v);
+            }
         }
     }
 }
@@ -467,7 +470,7 @@ __device__ __forceinline__ void contract_halves(const T *src, T *dst, const T *_
 // point then reads its three columns and forms w adj(J) adj(J)^T / detJ in
 // registers (the same expressions as the set-up kernel), instead of reading
 // six factors per point from HBM.
-template <int P, int Q, bool COLLOC, int MODE, bool VARK, typename T, int G, int NT, int VC, bool OTF = false>
+template <int P, int Q, bool COLLOC, int MODE, bool VARK, typename T, int G, int NT, int VC, bool OTF, bool DET>
 __global__ void __launch_bounds__(NT)
 k_apply(const T *__restrict__ bas, const int nex, const int ney, const int nvec, const int32_t *__restrict__ offsets,
         const T *__restrict__ qdata, const double *__restrict__ kappa, const double *__restrict__ wdet,
@@ -694,7 +697,7 @@ k_apply(const T *__restrict__ bas, const int nex, const int ney, const int nvec,
             }
         }
         group_sync<NT>();
-        scatter_add<P, Q, G, NT, VC, T>(sout, off, y, nvec, v0, nvalid, tid, ebuf, e0);
+        scatter_add<P, Q, G, NT, VC, DET, T>(sout, off, y, nvec, v0, nvalid, tid, ebuf, e0);
         group_sync<NT>();
     }
 }
@@ -723,7 +726,7 @@ __device__ __forceinline__ void load_mass_weights(T (&w)[RQ], const T *__restric
     }
 }
 
-template <int P, int Q, bool COLLOC, typename T, int G, int NT, int VC>
+template <int P, int Q, bool COLLOC, typename T, int G, int NT, int VC, bool DET>
 __global__ void __launch_bounds__(NT)
 k_mass(const T *__restrict__ bas, const int nex, const int64_t ngroups, const int nvec, const int chain,
        const int32_t *__restrict__ offsets, const T *__restrict__ qdata, const T *__restrict__ x, T *__restrict__ y,
@@ -789,7 +792,7 @@ k_mass(const T *__restrict__ bas, const int nex, const int64_t ngroups, const in
             contract<0, Q, P, P, P, GV, NT, Q, 1>(s0, s0, bas + basis_btf(P, Q), tid);
         }
         group_sync<NT>();
-        scatter_add<P, Q, G, NT, VC, T>(s0, off, y, nvec, v0, gpos.nvalid, tid, ebuf, gpos.e0);
+        scatter_add<P, Q, G, NT, VC, DET, T>(s0, off, y, nvec, v0, gpos.nvalid, tid, ebuf, gpos.e0);
         group_sync<NT>();
         if (!more) break;
         if (newgrp) {
@@ -1151,7 +1154,7 @@ __device__ __forceinline__ void gf_zt(T *A, const T *Bb, const T *__restrict__ b
 
 // PF: the lane's geometric factors are loaded at the start of the element group (as in k_apply);
 // otherwise in the pointwise stage, keeping their registers free through the forward stages.
-template <int P, int Q, bool VARK, typename T, int G, int NT, bool PF>
+template <int P, int Q, bool VARK, typename T, int G, int NT, bool PF, bool DET>
 __global__ void __launch_bounds__(NT)
 k_apply_gf(const T *__restrict__ bas, const int nex, const int nvec, const int32_t *__restrict__ offsets,
            const T *__restrict__ qdata, const double *__restrict__ kappa, const T *__restrict__ x, T *__restrict__ y,
@@ -1225,7 +1228,7 @@ k_apply_gf(const T *__restrict__ bas, const int nex, const int nvec, const int32
         group_sync<NT>();
         gf_zt<P, Q, G, NT, T>(A, Bb, bas, tid);
         group_sync<NT>();
-        scatter_add<P, Q, G, NT, 1, T>(A, off, y, nvec, v0, nvalid, tid, ebuf, e0);
+        scatter_add<P, Q, G, NT, 1, DET, T>(A, off, y, nvec, v0, nvalid, tid, ebuf, e0);
         group_sync<NT>();
     }
 }
@@ -1241,7 +1244,7 @@ static hipError_t prepare_lds(K kernel, size_t lds)
     return hipSuccess;
 }
 
-template <int P, int Q, bool COLLOC, int MODE, bool VARK, typename T, int V, bool OTF = false>
+template <int P, int Q, bool COLLOC, int MODE, bool VARK, typename T, int V, bool OTF, bool DET>
 static hipError_t launch_apply_v(const ApplyLaunch &a)
 {
     constexpr int G = variant_g(Q, V, MODE), NT = variant_nt(Q, V), VC = variant_vc(V);
@@ -1254,7 +1257,7 @@ static hipError_t launch_apply_v(const ApplyLaunch &a)
         const int chain = a.chain > 0 ? a.chain : 1;
         const int64_t ngroups = (int64_t)a.v.ney * a.v.nez * ((a.v.nex + G - 1) / G);
         const int64_t nblk = (ngroups + chain - 1) / chain;
-        auto kern = k_mass<P, Q, COLLOC, T, G, NT, VC>;
+        auto kern = k_mass<P, Q, COLLOC, T, G, NT, VC, DET>;
         const hipError_t e = prepare_lds(kern, lds);
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL(kern, dim3((unsigned)nblk), dim3(NT), lds, a.stream, static_cast<const T *>(a.basis_dev),
@@ -1263,7 +1266,7 @@ static hipError_t launch_apply_v(const ApplyLaunch &a)
         return hipGetLastError();
     } else {
         const int64_t nblk = (int64_t)a.v.ney * a.v.nez * ((a.v.nex + G - 1) / G);
-        auto kern = k_apply<P, Q, COLLOC, MODE, VARK, T, G, NT, VC, OTF>;
+        auto kern = k_apply<P, Q, COLLOC, MODE, VARK, T, G, NT, VC, OTF, DET>;
         const hipError_t e = prepare_lds(kern, lds);
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL(kern, dim3((unsigned)nblk), dim3(NT), lds, a.stream, static_cast<const T *>(a.basis_dev),
@@ -1274,7 +1277,7 @@ static hipError_t launch_apply_v(const ApplyLaunch &a)
     }
 }
 
-template <int P, int Q, bool COLLOC, int MODE, bool VARK, typename T, int V, bool OTF = false>
+template <int P, int Q, bool COLLOC, int MODE, bool VARK, typename T, int V, bool OTF, bool DET>
 static hipError_t launch_apply_gfv(const ApplyLaunch &a)
 {
     // the factored-gradient kernel: diffusion with Gauss points (not collocated), stored factors
@@ -1290,7 +1293,7 @@ static hipError_t launch_apply_gfv(const ApplyLaunch &a)
             return hipErrorInvalidValue;
         } else {
             const int64_t nblk = (int64_t)a.v.ney * a.v.nez * ((a.v.nex + G - 1) / G);
-            auto kern = k_apply_gf<P, Q, VARK, T, G, NT, PF>;
+            auto kern = k_apply_gf<P, Q, VARK, T, G, NT, PF, DET>;
             const hipError_t e = prepare_lds(kern, lds);
             if (e != hipSuccess) return e;
             hipLaunchKernelGGL(kern, dim3((unsigned)nblk), dim3(NT), lds, a.stream,
@@ -1302,27 +1305,37 @@ static hipError_t launch_apply_gfv(const ApplyLaunch &a)
     }
 }
 
+template <int P, int Q, bool COLLOC, int MODE, bool VARK, typename T, bool OTF, bool DET>
+static hipError_t launch_apply_vd(const ApplyLaunch &a)
+{
+    switch (a.variant) {
+    case 9: return launch_apply_gfv<P, Q, COLLOC, MODE, VARK, T, 9, OTF, DET>(a);
+    case 10: return launch_apply_gfv<P, Q, COLLOC, MODE, VARK, T, 10, OTF, DET>(a);
+    case 11: return launch_apply_gfv<P, Q, COLLOC, MODE, VARK, T, 11, OTF, DET>(a);
+    case 12: return launch_apply_gfv<P, Q, COLLOC, MODE, VARK, T, 12, OTF, DET>(a);
+    case 13: return launch_apply_gfv<P, Q, COLLOC, MODE, VARK, T, 13, OTF, DET>(a);
+    case 14: return launch_apply_gfv<P, Q, COLLOC, MODE, VARK, T, 14, OTF, DET>(a);
+    case 8: return launch_apply_v<P, Q, COLLOC, MODE, VARK, T, 8, OTF, DET>(a);
+    case 0: return launch_apply_v<P, Q, COLLOC, MODE, VARK, T, 0, OTF, DET>(a);
+    case 1: return launch_apply_v<P, Q, COLLOC, MODE, VARK, T, 1, OTF, DET>(a);
+    case 2: return launch_apply_v<P, Q, COLLOC, MODE, VARK, T, 2, OTF, DET>(a);
+    case 3: return launch_apply_v<P, Q, COLLOC, MODE, VARK, T, 3, OTF, DET>(a);
+    case 4: return launch_apply_v<P, Q, COLLOC, MODE, VARK, T, 4, OTF, DET>(a);
+    case 5: return launch_apply_v<P, Q, COLLOC, MODE, VARK, T, 5, OTF, DET>(a);
+    case 6: return launch_apply_v<P, Q, COLLOC, MODE, VARK, T, 6, OTF, DET>(a);
+    case 7: return launch_apply_v<P, Q, COLLOC, MODE, VARK, T, 7, OTF, DET>(a);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+// The deterministic (element-buffer) form is a separate instantiation; the load vector keeps atomics.
 template <int P, int Q, bool COLLOC, int MODE, bool VARK, typename T, bool OTF = false>
 static hipError_t launch_apply_t(const ApplyLaunch &a)
 {
-    switch (a.variant) {
-    case 9: return launch_apply_gfv<P, Q, COLLOC, MODE, VARK, T, 9, OTF>(a);
-    case 10: return launch_apply_gfv<P, Q, COLLOC, MODE, VARK, T, 10, OTF>(a);
-    case 11: return launch_apply_gfv<P, Q, COLLOC, MODE, VARK, T, 11, OTF>(a);
-    case 12: return launch_apply_gfv<P, Q, COLLOC, MODE, VARK, T, 12, OTF>(a);
-    case 13: return launch_apply_gfv<P, Q, COLLOC, MODE, VARK, T, 13, OTF>(a);
-    case 14: return launch_apply_gfv<P, Q, COLLOC, MODE, VARK, T, 14, OTF>(a);
-    case 8: return launch_apply_v<P, Q, COLLOC, MODE, VARK, T, 8, OTF>(a);
-    case 0: return launch_apply_v<P, Q, COLLOC, MODE, VARK, T, 0, OTF>(a);
-    case 1: return launch_apply_v<P, Q, COLLOC, MODE, VARK, T, 1, OTF>(a);
-    case 2: return launch_apply_v<P, Q, COLLOC, MODE, VARK, T, 2, OTF>(a);
-    case 3: return launch_apply_v<P, Q, COLLOC, MODE, VARK, T, 3, OTF>(a);
-    case 4: return launch_apply_v<P, Q, COLLOC, MODE, VARK, T, 4, OTF>(a);
-    case 5: return launch_apply_v<P, Q, COLLOC, MODE, VARK, T, 5, OTF>(a);
-    case 6: return launch_apply_v<P, Q, COLLOC, MODE, VARK, T, 6, OTF>(a);
-    case 7: return launch_apply_v<P, Q, COLLOC, MODE, VARK, T, 7, OTF>(a);
-    default: return hipErrorInvalidValue;
+    if constexpr (MODE != kRhs) {
+        if (a.ebuf) return launch_apply_vd<P, Q, COLLOC, MODE, VARK, T, OTF, true>(a);
     }
+    return launch_apply_vd<P, Q, COLLOC, MODE, VARK, T, OTF, false>(a);
 }
 
 template <int P, int Q, bool COLLOC>

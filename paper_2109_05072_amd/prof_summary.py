@@ -40,23 +40,27 @@ def kernel_source_hash(sources=KERNEL_SOURCES) -> str:
 
 def _short(name: str) -> str:
     m = re.match(r"void mfhex::k_apply<(\d+), (\d+), (\w+), (\d), (\w+), (\w+), (\d+), (\d+)(?:, (\d+))?"
-                 r"(?:, (true|false))?>", name)
+                 r"(?:, (true|false))?(?:, (true|false))?>", name)
     if m:
-        P, Q, colloc, mode, vark, T, G, NT, VC, otf = m.groups()
+        P, Q, colloc, mode, vark, T, G, NT, VC, otf, det = m.groups()
         kind = {"0": "mass", "1": "diffusion", "2": "rhs"}[mode]
         vc = f" VC={VC}" if VC and VC != "1" else ""
         geo = " otf" if otf == "true" else ""
-        return f"k_apply p={int(P) - 1} q={Q} {kind}{' kappa' if vark == 'true' else ''}{geo} {T} G={G} NT={NT}{vc}"
-    m = re.match(r"void mfhex::k_apply_gf<(\d+), (\d+), (\w+), (\w+), (\d+), (\d+), (\w+)>", name)
+        dt = " det" if det == "true" else ""
+        return (f"k_apply p={int(P) - 1} q={Q} {kind}{' kappa' if vark == 'true' else ''}{geo} {T} G={G} NT={NT}"
+                f"{vc}{dt}")
+    m = re.match(r"void mfhex::k_apply_gf<(\d+), (\d+), (\w+), (\w+), (\d+), (\d+), (\w+)(?:, (true|false))?>", name)
     if m:
-        P, Q, vark, T, G, NT, pf = m.groups()
+        P, Q, vark, T, G, NT, pf, det = m.groups()
         late = "" if pf == "true" else " late-factors"
-        return f"k_apply_gf p={int(P) - 1} q={Q} diffusion{' kappa' if vark == 'true' else ''} {T} G={G} NT={NT}{late}"
-    m = re.match(r"void mfhex::k_mass<(\d+), (\d+), (\w+), (\w+), (\d+), (\d+), (\d+)>", name)
+        dt = " det" if det == "true" else ""
+        return (f"k_apply_gf p={int(P) - 1} q={Q} diffusion{' kappa' if vark == 'true' else ''} {T} G={G} NT={NT}"
+                f"{late}{dt}")
+    m = re.match(r"void mfhex::k_mass<(\d+), (\d+), (\w+), (\w+), (\d+), (\d+), (\d+)(?:, (true|false))?>", name)
     if m:
-        P, Q, colloc, T, G, NT, VC = m.groups()
+        P, Q, colloc, T, G, NT, VC, det = m.groups()
         vc = f" VC={VC}" if VC != "1" else ""
-        return f"k_mass p={int(P) - 1} q={Q} {T} G={G} NT={NT}{vc}"
+        return f"k_mass p={int(P) - 1} q={Q} {T} G={G} NT={NT}{vc}{' det' if det == 'true' else ''}"
     m = re.match(r"void mfhex::tet::\(anonymous namespace\)::k_tet_apply<(\d+), (\d+)>", name)
     if m:
         return f"k_tet_apply p={m.group(1)} q={m.group(2)}"
@@ -122,10 +126,13 @@ def traffic_summary(fetch_dir: str, write_dir: str, command: str) -> str:
 def counter_summary(dirs, command: str, sources=KERNEL_SOURCES) -> str:
     """Per-kernel averages of every counter found in the ``--pmc`` runs under `dirs` (one directory per
     pass), plus derived ratios where their inputs were collected:
-      waves_per_simd  = SQ_WAVE_CYCLES / (GRBM_GUI_ACTIVE / 8 XCDs) / 1024 SIMDs  (mean resident waves)
-      valu_busy       = SQ_ACTIVE_INST_VALU / SQ_WAVE_CYCLES x waves_per_simd  (share of SIMD cycles
-                        issuing VALU; the SQ cycle counters share one unit, so the ratio is unit-free)
+      waves_per_simd  = 4 SQ_WAVE_CYCLES / (GRBM_GUI_ACTIVE / 8 XCDs) / 1024 SIMDs  (mean resident waves;
+                        the SQ wave-cycle counters count quad-cycles, GRBM_GUI_ACTIVE single cycles summed
+                        over the 8 XCDs)
+      valu_busy       = 4 SQ_ACTIVE_INST_VALU / (GRBM_GUI_ACTIVE / 8) / 1024  (share of SIMD cycles issuing
+                        VALU instructions)
       wait_any/wave   = SQ_WAIT_ANY / SQ_WAVE_CYCLES, wait_inst_any/wave = SQ_WAIT_INST_ANY / SQ_WAVE_CYCLES
+                        (shares of a wave's resident cycles; same unit on both sides)
       lds_conflict    = SQ_LDS_BANK_CONFLICT / SQ_LDS_IDX_ACTIVE
     Counter values are per dispatch, summed over the GPU by rocprofv3."""
     vals = defaultdict(lambda: defaultdict(list))
@@ -135,9 +142,9 @@ def counter_summary(dirs, command: str, sources=KERNEL_SOURCES) -> str:
     names = sorted({c for k in vals for c in vals[k]})
     out = [f"# rocprofv3 counters per dispatch (mean over dispatches)", f"# command: {command}",
            f"# kernel source hash: {kernel_source_hash(sources)}",
-           "# derived: waves_per_simd = SQ_WAVE_CYCLES/(GRBM_GUI_ACTIVE/8)/1024; valu_busy = "
-           "SQ_ACTIVE_INST_VALU/SQ_WAVE_CYCLES*waves_per_simd; wait ratios per wave cycle; "
-           "lds_conflict = SQ_LDS_BANK_CONFLICT/SQ_LDS_IDX_ACTIVE"]
+           "# derived (SQ wave-cycle counters count quad-cycles): waves_per_simd = "
+           "4*SQ_WAVE_CYCLES/(GRBM_GUI_ACTIVE/8)/1024; valu_busy = 4*SQ_ACTIVE_INST_VALU/(GRBM_GUI_ACTIVE/8)/1024; "
+           "wait ratios per wave cycle; lds_conflict = SQ_LDS_BANK_CONFLICT/SQ_LDS_IDX_ACTIVE"]
     for k in vals:
         sk = _short(k)
         if not (sk.startswith("k_apply") or sk.startswith("k_mass") or sk.startswith("k_tet")):
@@ -149,10 +156,10 @@ def counter_summary(dirs, command: str, sources=KERNEL_SOURCES) -> str:
                 out.append(f"    {c:<28} {m[c]:.4g}")
         der = {}
         if "SQ_WAVE_CYCLES" in m and "GRBM_GUI_ACTIVE" in m and m["GRBM_GUI_ACTIVE"] > 0:
-            wps = m["SQ_WAVE_CYCLES"] / (m["GRBM_GUI_ACTIVE"] / 8) / 1024
-            der["waves_per_simd"] = wps
+            simd_cycles = m["GRBM_GUI_ACTIVE"] / 8 * 1024
+            der["waves_per_simd"] = 4 * m["SQ_WAVE_CYCLES"] / simd_cycles
             if "SQ_ACTIVE_INST_VALU" in m:
-                der["valu_busy"] = m["SQ_ACTIVE_INST_VALU"] / m["SQ_WAVE_CYCLES"] * wps
+                der["valu_busy"] = 4 * m["SQ_ACTIVE_INST_VALU"] / simd_cycles
         if "SQ_WAVE_CYCLES" in m and m["SQ_WAVE_CYCLES"] > 0:
             for c in ("SQ_WAIT_ANY", "SQ_WAIT_INST_ANY", "SQ_WAIT_INST_LDS", "SQ_ACTIVE_INST_LDS",
                       "SQ_ACTIVE_INST_SCA", "SQ_ACTIVE_INST_VMEM", "SQ_ACTIVE_INST_VALU"):
