@@ -117,12 +117,16 @@ constexpr bool split_stages(int Q, int mode, int G, int NT, int VC)
 // (one element per group), sharing the geometric factors and reading /
 // writing each node's chunk as one contiguous run.
 constexpr int kNumVariants = 15;
+// At q = 6 and 7 variant 4 fills the lanes: every contraction of the diffusion
+// kernel runs over G q^2 lines (q^2 = 36, 49), so 7 and 5 elements per
+// 256-thread group give 252 and 245 lines, where groups of 1 or 2 elements
+// leave 44-62% of the lanes idle.
 constexpr int kVarG[9][5] = {
-    {16, 8, 32, 16, 32}, {8, 4, 16, 8, 16}, {4, 2, 8, 4, 8}, {4, 2, 8, 2, 8}, {1, 2, 1, 2, 4},
-    {1, 2, 1, 1, 2},     {1, 1, 1, 2, 2},   {2, 1, 1, 1, 2}, {1, 1, 1, 2, 2}};
+    {16, 8, 32, 16, 32}, {8, 4, 16, 8, 16}, {4, 2, 8, 4, 8}, {4, 2, 8, 2, 8}, {1, 2, 1, 2, 7},
+    {1, 2, 1, 1, 5},     {1, 1, 1, 2, 2},   {2, 1, 1, 1, 2}, {1, 1, 1, 2, 2}};
 constexpr int kVarNT[9][5] = {
     {64, 64, 64, 128, 128},  {64, 64, 64, 128, 128},  {64, 64, 64, 128, 128},
-    {128, 64, 128, 128, 256}, {64, 64, 128, 128, 128}, {64, 128, 128, 256, 64},
+    {128, 64, 128, 128, 256}, {64, 64, 128, 128, 256}, {64, 128, 128, 256, 256},
     {128, 256, 64, 128, 64}, {256, 128, 64, 256, 256}, {256, 128, 64, 128, 256}};
 constexpr int variant_vc(int v) { return v < 5 || v >= 9 ? 1 : v == 5 ? 2 : v == 6 ? 4 : v == 7 ? 8 : 16; }
 // Variants 9 .. 14: the factored-gradient diffusion kernel (Gauss points, one vector at a time;
@@ -176,12 +180,13 @@ constexpr size_t kMaxLds = 98304;
 // mass operator, the pipeline depth measured fastest (median of interleaved
 // timings at about 1e7 DOFs on perturbed box meshes, Gauss q = p+2); orders
 // not measured there keep variant 0.
-constexpr int kDefVariantDiff[9] = {0, 0, 0, 4, 3, 0, 0, 1, 0};
+constexpr int kDefVariantDiff[9] = {0, 0, 0, 4, 4, 4, 0, 1, 0};
 // FP32 diffusion (the operator inside mixed-precision CG): half the register and LDS footprint
-// favours two-element groups at q = 7 and 8 (5-13% and 20-27% faster than the FP64 choice at 1e7
-// and 3e7 nodes); at q = 9 the best choice changes with the mesh size, and it and the other q
-// keep the FP64 choice.
-constexpr int kDefVariantDiff32[9] = {0, 0, 0, 4, 3, 1, 3, 1, 0};
+// favours two-element groups at q = 8 (20-27% faster than the FP64 choice at 1e7 and 3e7 nodes);
+// the lane-filling groups of q = 6 and 7 are 6% and 6-12% faster than the earlier two-element
+// choices; at q = 9 the best choice changes with the mesh size, and it and the other q keep the
+// FP64 choice.
+constexpr int kDefVariantDiff32[9] = {0, 0, 0, 4, 4, 4, 3, 1, 0};
 constexpr int kDefVariantMass[9] = {0, 0, 0, 3, 3, 1, 3, 0, 4};
 constexpr int kDefChainMass[9] = {2, 2, 2, 4, 2, 4, 4, 4, 2};
 // Device basis block (elements): B [Q][P], B^T [P][Q], D [Q][Q], D^T [Q][Q],
