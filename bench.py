@@ -9,7 +9,10 @@ homogeneous Dirichlet, input U[-1,1].  Synthetic inputs stand in for the CEED
 bake-off meshes.  One step = one apply at every order; value = nodes
 processed per second over the step (GDOF/s).
 
-Per order the apply is bracketed by HIP events on the launch stream; the
+The timed region runs the K steps order by order (K back-to-back applies of
+each operator, as an operator is applied inside CG; --interleaved runs them
+step by step).  Per order each apply is bracketed by HIP events on the launch
+stream; the
 roofline fraction uses the algorithmic bytes of one apply,
   8 N (x) + 8 N (y) + 4 E (p+1)^3 (restriction) + 48 E q^3 (geometric factors),
 over the measured duration, against 8 TB/s.  The CPU baseline times the FP64
@@ -119,6 +122,8 @@ def main():
     ap.add_argument("--otf", action="store_true",
                     help="diffusion with the geometric factors evaluated in the kernel (no stored factors)")
     ap.add_argument("--sweep", action="store_true", help="report the time of every launch variant (stderr)")
+    ap.add_argument("--interleaved", action="store_true",
+                    help="time the steps one by one (one apply of every order per step) instead of order by order")
     ap.add_argument("--calib-copy", action="store_true",
                     help="after timing, copy 1 GiB device-to-device twice (a kernel of known traffic, "
                          "used to scale the HBM byte counters)")
@@ -161,12 +166,23 @@ def main():
                for _ in range(args.steps)] for p in orders}
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for s in range(args.steps):
+    if args.interleaved:
+        # step by step: one apply of every order per step
+        for s in range(args.steps):
+            for p in orders:
+                e0, e1 = evs[p][s]
+                e0.record()
+                ops[p].apply(xs[p], ys[p])
+                e1.record()
+    else:
+        # the same K steps order by order: K back-to-back applies of each operator (t_apply of the
+        # measurement plan; an operator inside CG is applied back to back the same way)
         for p in orders:
-            e0, e1 = evs[p][s]
-            e0.record()
-            ops[p].apply(xs[p], ys[p])
-            e1.record()
+            for s in range(args.steps):
+                e0, e1 = evs[p][s]
+                e0.record()
+                ops[p].apply(xs[p], ys[p])
+                e1.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
 
@@ -218,7 +234,8 @@ def main():
                    if args.kind == "diffusion" else
                                (f"BP1 mass apply FP64, Gauss q=p+2, p={','.join(map(str, orders))}, "
                                 f"~{args.dofs:.0e} DOFs per order, perturbed hex mesh"),
-                   "orders": orders, "dofs_per_step": dofs_per_step},
+                   "orders": orders, "dofs_per_step": dofs_per_step,
+                   "timing": "interleaved steps" if args.interleaved else "steps order by order (back-to-back applies)"},
         "roofline": ({"bound": "hbm", "kernel": dom_name,
                       "achieved": dom["alg_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                       "frac": dom["hbm_frac"], "traffic": traffic.get(dom_name),

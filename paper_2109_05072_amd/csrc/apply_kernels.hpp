@@ -470,7 +470,8 @@ __device__ __forceinline__ void contract_halves(const T *src, T *dst, const T *_
 // point then reads its three columns and forms w adj(J) adj(J)^T / detJ in
 // registers (the same expressions as the set-up kernel), instead of reading
 // six factors per point from HBM.
-template <int P, int Q, bool COLLOC, int MODE, bool VARK, typename T, int G, int NT, int VC, bool OTF, bool DET>
+template <int P, int Q, bool COLLOC, int MODE, bool VARK, typename T, int G, int NT, int VC, bool OTF, bool DET,
+          bool STAGE = false>
 __global__ void __launch_bounds__(NT)
 k_apply(const T *__restrict__ bas, const int nex, const int ney, const int nvec, const int32_t *__restrict__ offsets,
         const T *__restrict__ qdata, const double *__restrict__ kappa, const double *__restrict__ wdet,
@@ -493,11 +494,21 @@ k_apply(const T *__restrict__ bas, const int nex, const int ney, const int nvec,
     double *const sV = reinterpret_cast<double *>(SPLIT ? s3 + GV * L::BUF : s2 + GV * L::BUF);
     double *const sR = sV + G * 24;
     double *const sJ = sR + 2 * Q;
+    // staged scatter of multi-vector chunks: element values [P^3][SC - VC], then offsets [P^3]
+    constexpr int P3 = P * P * P;
+    static_assert(!STAGE || (staged_scatter(MODE, VC, sizeof(T)) && !DET), "staged scatter: multi-vector diffusion");
+    constexpr int SC = scatter_run(VC, sizeof(T));
+    T *const sst = s2 + GV * L::BUF;
+    int32_t *const soff = reinterpret_cast<int32_t *>(sst + P3 * (SC - VC));
     const int tid = threadIdx.x;
     const int half = tid / NT2, lane = tid - half * NT2;  // split stages: wave-uniform halves
     const GroupPos gpos = group_pos<G>(xcd_block(blockIdx.x, gridDim.x), nex);
     const int64_t e0 = gpos.e0;
     const int nvalid = gpos.nvalid;
+    if constexpr (STAGE) {
+        static_assert(G == 1 && !SPLIT && !OTF, "staged scatter: one element, plain stages");
+        for (int t = tid; t < P3; t += NT) soff[t] = __builtin_nontemporal_load(&offsets[e0 * P3 + t]);
+    }
 
     int32_t off[NodeIO<P, G, NT, VC>::NR];
     load_offsets<P, G, NT, VC>(off, offsets, e0, nvalid, tid);
@@ -697,7 +708,33 @@ k_apply(const T *__restrict__ bas, const int nex, const int ney, const int nvec,
             }
         }
         group_sync<NT>();
-        scatter_add<P, Q, G, NT, VC, DET, T>(sout, off, y, nvec, v0, nvalid, tid, ebuf, e0);
+        if constexpr (STAGE) {
+            // the run of vectors this chunk belongs to: [r0, r0 + SC); nst of them are staged already
+            const int r0 = v0 - v0 % SC, nst = v0 - r0;
+            if ((v0 + VC) % SC != 0 && v0 + VC < nvec) {
+                // not the run's last chunk: keep its element values
+                for (int t = tid; t < P3 * VC; t += NT) {
+                    const int vc = t % VC, u = t / VC;
+                    const int i = u % P, j = (u / P) % P, k = u / (P * P);
+                    sst[u * (SC - VC) + nst + vc] = sout[vc * L::BUF + i + L::PITCH * j + L::PLANE * k];
+                }
+            } else {
+                // the run's last chunk: add all its vectors, consecutive lanes on consecutive vectors of a node
+                const int run = nst + VC;
+                for (int t = tid; t < P3 * run; t += NT) {
+                    const int w = t % run, u = t / run;
+                    const int32_t o = soff[u];
+                    if (o >= 0 && r0 + w < nvec) {
+                        const int i = u % P, j = (u / P) % P, k = u / (P * P);
+                        const T v = w < nst ? sst[u * (SC - VC) + w]
+                                            : sout[(w - nst) * L::BUF + i + L::PITCH * j + L::PLANE * k];
+                        unsafeAtomicAdd(&y[(int64_t)o * nvec + r0 + w], v);
+                    }
+                }
+            }
+        } else {
+            scatter_add<P, Q, G, NT, VC, DET, T>(sout, off, y, nvec, v0, nvalid, tid, ebuf, e0);
+        }
         group_sync<NT>();
     }
 }
@@ -1248,7 +1285,7 @@ template <int P, int Q, bool COLLOC, int MODE, bool VARK, typename T, int V, boo
 static hipError_t launch_apply_v(const ApplyLaunch &a)
 {
     constexpr int G = variant_g(Q, V, MODE), NT = variant_nt(Q, V), VC = variant_vc(V);
-    constexpr size_t lds = apply_lds(Q, MODE, sizeof(T), V, OTF);
+    constexpr size_t lds = apply_lds(P, Q, MODE, sizeof(T), V, OTF);
     // chunked multi-vector variants exist for the plain mass / diffusion operators only
     if constexpr ((VC > 1 && (MODE == kRhs || VARK || OTF)) || lds > kMaxLds) {
         (void)a;
@@ -1266,14 +1303,23 @@ static hipError_t launch_apply_v(const ApplyLaunch &a)
         return hipGetLastError();
     } else {
         const int64_t nblk = (int64_t)a.v.ney * a.v.nez * ((a.v.nex + G - 1) / G);
-        auto kern = k_apply<P, Q, COLLOC, MODE, VARK, T, G, NT, VC, OTF, DET>;
-        const hipError_t e = prepare_lds(kern, lds);
-        if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(kern, dim3((unsigned)nblk), dim3(NT), lds, a.stream, static_cast<const T *>(a.basis_dev),
-                           a.v.nex, a.v.ney, a.nvec, a.v.offsets, static_cast<const T *>(a.v.qdata), a.v.kappa,
-                           a.wdet, a.vert, static_cast<const T *>(a.x), static_cast<T *>(a.y),
-                           static_cast<T *>(a.ebuf));
-        return hipGetLastError();
+        auto go = [&](auto kern, size_t lds_bytes) {
+            const hipError_t e = prepare_lds(kern, lds_bytes);
+            if (e != hipSuccess) return e;
+            hipLaunchKernelGGL(kern, dim3((unsigned)nblk), dim3(NT), lds_bytes, a.stream,
+                               static_cast<const T *>(a.basis_dev), a.v.nex, a.v.ney, a.nvec, a.v.offsets,
+                               static_cast<const T *>(a.v.qdata), a.v.kappa, a.wdet, a.vert,
+                               static_cast<const T *>(a.x), static_cast<T *>(a.y), static_cast<T *>(a.ebuf));
+            return hipGetLastError();
+        };
+        // several chunks per launch: staged scatter in runs of at least 64 bytes per node
+        if constexpr (staged_scatter(MODE, VC, sizeof(T)) && !DET && !VARK && !OTF) {
+            constexpr size_t lds_st = apply_lds(P, Q, MODE, sizeof(T), V, OTF, true);
+            if constexpr (lds_st <= kMaxLds) {
+                if (a.nvec > VC) return go(k_apply<P, Q, COLLOC, MODE, VARK, T, G, NT, VC, OTF, DET, true>, lds_st);
+            }
+        }
+        return go(k_apply<P, Q, COLLOC, MODE, VARK, T, G, NT, VC, OTF, DET>, lds);
     }
 }
 
@@ -1287,7 +1333,7 @@ static hipError_t launch_apply_gfv(const ApplyLaunch &a)
     } else {
         constexpr int G = variant_g(Q, V, MODE), NT = variant_nt(Q, V);
         constexpr bool PF = gf_prefetch(V);
-        constexpr size_t lds = apply_lds(Q, MODE, sizeof(T), V, OTF);
+        constexpr size_t lds = apply_lds(P, Q, MODE, sizeof(T), V, OTF);
         if constexpr (lds > kMaxLds) {
             (void)a;
             return hipErrorInvalidValue;

@@ -163,7 +163,7 @@ bool valid_variant(const mfhex_op_s &op, int prec, int variant)
     if (otf && variant_vc(variant) > 1) return false;  // in-kernel factors: single-vector variants
     // the factored-gradient kernel: diffusion with Gauss points and stored factors
     if (variant_gf(variant) && (mode_of(op) != kDiff || op.basis.colloc || otf)) return false;
-    return apply_lds(op.Q, mode_of(op), prec == MFHEX_F32 ? 4 : 8, variant, otf) <= kMaxLds;
+    return apply_lds(op.P, op.Q, mode_of(op), prec == MFHEX_F32 ? 4 : 8, variant, otf) <= kMaxLds;
 }
 
 int default_variant(const mfhex_op_s &op, int prec, int nvec)
@@ -177,7 +177,15 @@ int default_variant(const mfhex_op_s &op, int prec, int nvec)
                                            : kDefVariantDiff)[op.Q - 2];
         return valid_variant(op, prec, v) ? v : 0;
     }
-    for (int v = 8; v >= 5; --v)  // the multi-vector chunk variants
+    // (with the scatter staging that several chunks need, the chunk must still leave room for two
+    // thread groups per compute unit)
+    const int eb = prec == MFHEX_F32 ? 4 : 8;
+    for (int v = 8; v >= 5; --v) {  // the multi-vector chunk variants
+        if (variant_vc(v) > nvec || !valid_variant(op, prec, v)) continue;
+        const bool stage = nvec > variant_vc(v);
+        if (apply_lds(op.P, op.Q, mode_of(op), eb, v, false, stage) <= kLdsTwoGroups) return v;
+    }
+    for (int v = 8; v >= 5; --v)
         if (variant_vc(v) <= nvec && valid_variant(op, prec, v)) return v;
     return 0;
 }

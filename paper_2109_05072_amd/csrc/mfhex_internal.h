@@ -165,16 +165,31 @@ constexpr bool variant_split(int Q, int v, int mode)
 {
     return !variant_gf(v) && split_stages(Q, mode, variant_g(Q, v, mode), variant_nt(Q, v), variant_vc(v));
 }
-constexpr size_t apply_lds(int Q, int mode, int elem_bytes, int v, bool otf = false)
+// Multi-vector chunks of the diffusion kernel add their results to y in runs of at least 64 bytes
+// per node (8 FP64 or 16 FP32 vectors) when a launch has more vectors than one chunk: y is
+// node-major, and a chunk of fewer vectors would leave partly written lines in the L2 between
+// chunks, which go back to HBM as 32-byte partial writes.  The element values of all but the last
+// chunk of a run wait in LDS ([P^3][run - VC]), next to the element's restriction offsets ([P^3]
+// int32).  A launch whose vectors fit one chunk adds them directly.
+constexpr int scatter_run(int vc, int elem_bytes) { return vc * elem_bytes >= 64 ? vc : 64 / elem_bytes; }
+constexpr bool staged_scatter(int mode, int vc, int elem_bytes)
 {
-    return (size_t)variant_g(Q, v, mode) * variant_vc(v) * apply_nbuf(mode, variant_split(Q, v, mode)) * lds_buf(Q) *
-               elem_bytes +
-           (otf ? (size_t)otf_lds_doubles(Q, variant_g(Q, v, mode)) * 8 : 0);
+    return mode == 1 && vc > 1 && scatter_run(vc, elem_bytes) > vc;
+}
+constexpr size_t apply_lds(int P, int Q, int mode, int elem_bytes, int v, bool otf = false, bool stage = false)
+{
+    const int vc = variant_vc(v);
+    const size_t p3 = (size_t)P * P * P;
+    return (size_t)variant_g(Q, v, mode) * vc * apply_nbuf(mode, variant_split(Q, v, mode)) * lds_buf(Q) * elem_bytes +
+           (otf ? (size_t)otf_lds_doubles(Q, variant_g(Q, v, mode)) * 8 : 0) +
+           (stage && staged_scatter(mode, vc, elem_bytes) ? p3 * (scatter_run(vc, elem_bytes) - vc) * elem_bytes + p3 * 4
+                                                          : 0);
 }
 // Largest dynamic LDS of one thread group (gfx950 has 160 KB per CU; above 64 KB the kernel is
 // launched with a raised limit).  96 KB admits 8-vector chunks at q = 7, 4-vector chunks at q = 9
 // and 16-vector chunks at q = 6 while still leaving room for a second group on the CU.
 constexpr size_t kMaxLds = 98304;
+constexpr size_t kLdsTwoGroups = 81920;  // at most this much LDS leaves room for two thread groups per CU
 
 // Single-vector launch defaults per q (index q-2): the variant and, for the
 // mass operator, the pipeline depth measured fastest (median of interleaved

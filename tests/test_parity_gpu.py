@@ -119,14 +119,14 @@ def test_apply_fp32_matches_oracle(gpu_lib, p, kind, quad, dirichlet):
 
 @pytest.mark.parametrize("p", [5, 6, 7], ids=["p5-q7-default", "p6-q8-default-two-element", "p7-q9-default"])
 def test_fp32_default_launch_at_mixed_cg_orders(gpu_lib, p):
-    # the FP32 launch defaults of their own (two-element groups at q = 7 and 8, the FP64 choice at
-    # q = 9) on a mesh whose element rows leave a ragged last group, against the oracle and
-    # against the FP64 apply rounded to FP32 accuracy
-    op, pr = build(gpu_lib, 5, 4, 3, p, "diffusion", "gauss", True, f32=True)
+    # the FP32 launch defaults of their own (five-element groups at q = 7, two-element groups at
+    # q = 8, the FP64 choice at q = 9) on a mesh whose element rows leave a ragged last group (7 =
+    # 5 + 2 = 3 x 2 + 1), against the oracle and against the FP64 apply rounded to FP32 accuracy
+    op, pr = build(gpu_lib, 7, 3, 3, p, "diffusion", "gauss", True, f32=True)
     cfg = op.get_config(torch.float32)
     _say("fp32 default", p, cfg)
     if p in (5, 6):
-        assert cfg[1] == 2, cfg
+        assert cfg[1] == {5: 5, 6: 2}[p], cfg
     x = synth.uniform_vector(pr.n_nodes, seed=9)
     yo = oracle.apply(pr, x)
     y32 = host(op.apply(dev(x, torch.float32)))
