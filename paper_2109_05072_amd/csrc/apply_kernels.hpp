@@ -471,7 +471,7 @@ __device__ __forceinline__ void contract_halves(const T *src, T *dst, const T *_
 // registers (the same expressions as the set-up kernel), instead of reading
 // six factors per point from HBM.
 template <int P, int Q, bool COLLOC, int MODE, bool VARK, typename T, int G, int NT, int VC, bool OTF, bool DET,
-          bool STAGE = false>
+          bool STAGE = false, int LATE = 0>
 __global__ void __launch_bounds__(NT)
 k_apply(const T *__restrict__ bas, const int nex, const int ney, const int nvec, const int32_t *__restrict__ offsets,
         const T *__restrict__ qdata, const double *__restrict__ kappa, const double *__restrict__ wdet,
@@ -532,8 +532,11 @@ k_apply(const T *__restrict__ bas, const int nex, const int ney, const int nvec,
 
     // This lane's geometric factors, loaded once per element group and issued
     // first, so their HBM latency overlaps the gather and the forward
-    // contractions, and every chunk of vectors reuses them.
-    constexpr int NQD = MODE == kDiff && !OTF ? kQdDiff : 0;
+    // contractions, and every chunk of vectors reuses them (LATE > 0: loaded in
+    // the pointwise stage instead, LATE points at a time, which keeps their
+    // registers free through the contractions).
+    static_assert(LATE == 0 || (VC == 1 && !OTF && MODE == kDiff), "late factor loads: one-vector diffusion");
+    constexpr int NQD = MODE == kDiff && !OTF && LATE == 0 ? kQdDiff : 0;
     T qv[RQ][NQD > 0 ? NQD : 1];
     if constexpr (NQD > 0) {
 #pragma unroll
@@ -636,14 +639,27 @@ k_apply(const T *__restrict__ bas, const int nex, const int ney, const int nvec,
             {
                 // split stages write d/dt's factor product to s3 (s0 is the transposed gradient's output)
                 T *const st = SPLIT ? s3 : s0;
-#pragma unroll
+#pragma unroll(LATE > 0 ? LATE : RQ)
                 for (int k = 0; k < RQ; ++k) {
                     const int id = tid + k * NT;
                     if (id < NPT) {
                         const int g = id / Q3, pt = id - g * Q3;
                         const int a = pt % Q, b = (pt / Q) % Q, c = pt / Q2;
                         const int loc = a + L::PITCH * b + L::PLANE * c;
-                        const T *gm = qv[k];
+                        const T *gm = qv[LATE > 0 ? 0 : k];
+                        T gl[kQdDiff];
+                        if constexpr (LATE > 0) {
+                            const int64_t e = g < nvalid ? e0 + g : e0;
+                            const T *qd = qdata + e * (kQdDiff * Q3) + pt;
+#pragma unroll
+                            for (int m = 0; m < kQdDiff; ++m) gl[m] = __builtin_nontemporal_load(&qd[m * Q3]);
+                            if constexpr (VARK) {
+                                const T kap = T(kappa[e * Q3 + pt]);
+#pragma unroll
+                                for (int m = 0; m < kQdDiff; ++m) gl[m] *= kap;
+                            }
+                            gm = gl;
+                        }
                         double gotf[kQdDiff];
                         if constexpr (OTF) {
                             // columns dx/dr at (b, c), dx/ds at (a, c), dx/dt at (a, b) of element g
@@ -1319,7 +1335,8 @@ static hipError_t launch_apply_v(const ApplyLaunch &a)
                 if (a.nvec > VC) return go(k_apply<P, Q, COLLOC, MODE, VARK, T, G, NT, VC, OTF, DET, true>, lds_st);
             }
         }
-        return go(k_apply<P, Q, COLLOC, MODE, VARK, T, G, NT, VC, OTF, DET>, lds);
+        constexpr int LATE = MODE == kDiff && VC == 1 && !OTF ? variant_late(Q, V) : 0;
+        return go(k_apply<P, Q, COLLOC, MODE, VARK, T, G, NT, VC, OTF, DET, false, LATE>, lds);
     }
 }
 

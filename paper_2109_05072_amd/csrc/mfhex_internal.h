@@ -121,13 +121,22 @@ constexpr int kNumVariants = 15;
 // kernel runs over G q^2 lines (q^2 = 36, 49), so 7 and 5 elements per
 // 256-thread group give 252 and 245 lines, where groups of 1 or 2 elements
 // leave 44-62% of the lanes idle.
+// At q = 10 variant 2 loads each point's geometric factors in the pointwise stage (four points
+// at a time) instead of at the start of the element group: the prefetched factors of 8 points per
+// lane take 96 registers, so without them a 128-thread group fits five waves per SIMD instead of
+// two.  Measured against variant 0 it was 6% faster on one box and 5% slower on another, so it
+// is a tuner candidate, not the default.
 constexpr int kVarG[9][5] = {
     {16, 8, 32, 16, 32}, {8, 4, 16, 8, 16}, {4, 2, 8, 4, 8}, {4, 2, 8, 2, 8}, {1, 2, 1, 2, 7},
     {1, 2, 1, 1, 5},     {1, 1, 1, 2, 2},   {2, 1, 1, 1, 2}, {1, 1, 1, 2, 2}};
 constexpr int kVarNT[9][5] = {
     {64, 64, 64, 128, 128},  {64, 64, 64, 128, 128},  {64, 64, 64, 128, 128},
     {128, 64, 128, 128, 256}, {64, 64, 128, 128, 256}, {64, 128, 128, 256, 256},
-    {128, 256, 64, 128, 64}, {256, 128, 64, 256, 256}, {256, 128, 64, 128, 256}};
+    {128, 256, 64, 128, 64}, {256, 128, 64, 256, 256}, {256, 128, 128, 128, 256}};
+// points per factor-load batch in the pointwise stage (0: factors prefetched at the group start)
+constexpr int kVarLate[9][5] = {{0, 0, 0, 0, 0}, {0, 0, 0, 0, 0}, {0, 0, 0, 0, 0}, {0, 0, 0, 0, 0}, {0, 0, 0, 0, 0},
+                                {0, 0, 0, 0, 0}, {0, 0, 0, 0, 0}, {0, 0, 0, 0, 0}, {0, 0, 4, 0, 0}};
+constexpr int variant_late(int Q, int v) { return v < 5 ? kVarLate[Q - 2][v] : 0; }
 constexpr int variant_vc(int v) { return v < 5 || v >= 9 ? 1 : v == 5 ? 2 : v == 6 ? 4 : v == 7 ? 8 : 16; }
 // Variants 9 .. 14: the factored-gradient diffusion kernel (Gauss points, one vector at a time;
 // k_apply_gf): 9 .. 13 take the (elements, threads) pairs below per q and load the geometric
