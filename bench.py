@@ -9,7 +9,9 @@ homogeneous Dirichlet, input U[-1,1].  Synthetic inputs stand in for the CEED
 bake-off meshes.  One step = one apply at every order; value = nodes
 processed per second over the step (GDOF/s).
 
-The timed region runs the K steps order by order (K back-to-back applies of
+Before timing, each operator is autotuned on this GPU (mfhex_tune: every
+launch variant whose result agrees with the default, median of three rounds;
+--no-tune times the built-in defaults).  The timed region runs the K steps order by order (K back-to-back applies of
 each operator, as an operator is applied inside CG; --interleaved runs them
 step by step).  Per order each apply is bracketed by HIP events on the launch
 stream; the
@@ -118,7 +120,8 @@ def main():
                     help="also time Jacobi- and p-multigrid-preconditioned CG next to FP64 vs mixed CG")
     ap.add_argument("--tet", action="store_true",
                     help="also time the tetrahedral P_p diffusion apply (matrix-core basis products), p=2..6")
-    ap.add_argument("--tune", action="store_true", help="autotune the launch variant before timing")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="time the built-in launch defaults instead of autotuning each operator before timing")
     ap.add_argument("--otf", action="store_true",
                     help="diffusion with the geometric factors evaluated in the kernel (no stored factors)")
     ap.add_argument("--sweep", action="store_true", help="report the time of every launch variant (stderr)")
@@ -150,8 +153,8 @@ def main():
         ops[p], xs[p], ys[p] = op, x, torch.empty_like(x)
         if args.sweep:
             sweep_variants(op, x, p)
-        if args.tune:
-            op.tune()
+        if not args.no_tune:
+            op.tune()  # the launch variant for this operator on this GPU (untimed set-up)
         meta[p] = dict(ne=ne, N=op.n_nodes, E=op.n_elem, q=p + 2, epb=op.get_config())
         print(f"# setup p={p}: {ne}^3 elements, {op.n_nodes} DOFs, launch (variant, elems, threads, depth) "
               f"{meta[p]['epb']}",
@@ -268,7 +271,7 @@ def main():
         for r in per_p:
             r["read_ceiling_frac"] = round(r["alg_gbs"] / out["hbm_ceiling"]["read_gbs"], 4)
         # the second gate size of the sweep: about 1e8 nodes per order
-        out["per_order_1e8"] = per_order_sweep(orders, 1e8, steps=5)
+        out["per_order_1e8"] = per_order_sweep(orders, 1e8, steps=5, tune=not args.no_tune)
     if args.cg or default_extras:
         # the second half of the metric: FP64 vs mixed-precision CG to a 1e-10 relative residual at
         # about 3e7 nodes, p = 3, 5, 7 (preconditioned variants only with --cg)
@@ -355,9 +358,10 @@ def hbm_ceiling(nbytes: int = 4 << 30, reps: int = 5) -> dict:
     return out
 
 
-def per_order_sweep(orders, dofs: float, steps: int = 5) -> list:
-    """BP3 FP64 apply at about `dofs` nodes per order (one operator at a time): median of `steps`
-    event-timed applies after two warm-ups, with the roofline fraction against 8 TB/s."""
+def per_order_sweep(orders, dofs: float, steps: int = 5, tune: bool = True) -> list:
+    """BP3 FP64 apply at about `dofs` nodes per order (one operator at a time, autotuned unless
+    tune=False): median of `steps` event-timed back-to-back applies after two warm-ups, with the
+    roofline fraction against 8 TB/s."""
     import torch
     import synth
     import paper_2109_05072_amd as mf
@@ -368,6 +372,8 @@ def per_order_sweep(orders, dofs: float, steps: int = 5) -> list:
         op = mf.Operator(ne, ne, ne, p, vert, kind="diffusion", quad="gauss", dirichlet=True)
         x = torch.from_numpy(synth.uniform_vector(op.n_nodes)).cuda()
         y = torch.empty_like(x)
+        if tune:
+            op.tune()
         for _ in range(2):
             op.apply(x, y)
         ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]

@@ -15,8 +15,9 @@
  *   - Every function returns int: MFHEX_OK (0) or a negative MFHEX_ERR_*.
  *     Nothing aborts or throws; mfhex_last_error() gives a message.
  *   - "_dev" pointers are device (HBM) pointers owned by the CALLER; the
- *     library never allocates or frees device memory.  Host pointers are
- *     read during the call only.
+ *     library never allocates or frees device memory (its only device
+ *     storage is the fixed array of mfhex_apply_static, part of the loaded
+ *     code object).  Host pointers are read during the call only.
  *   - `stream` is a hipStream_t passed as void* (NULL = default stream).
  *     apply / apply_add / apply_adjoint / kappa_grad / diagonal / rhs /
  *     *_coords / mg_apply / tet_apply enqueue kernels only (outputs are
@@ -298,7 +299,8 @@ int mfhex_mg_level(mfhex_op op, int level, int32_t *p, int64_t *n_nodes, double 
  * fused kernel (elements per thread group, threads per group; for the mass
  * operator also pipeline depths 1, 2 and 4) on this operator, reject any whose
  * result differs from the default configuration by more than 1e-13 (relative,
- * max norm; 1e-5 for FP32), keep the fastest for this handle and append
+ * max norm; 1e-5 for FP32), time the others in three interleaved rounds of ten
+ * applies, keep the one with the smallest median for this handle and append
  * "<arch> kind quad p nvec prec variant depth" to the text cache
  * at cache_path (NULL: no file); handles created later read the file named by
  * the environment variable MFHEX_TUNE_CACHE.  scratch_dev: caller-owned
