@@ -110,6 +110,9 @@ def main():
                     help="diffusion = BP3 (default), mass = BP1")
     ap.add_argument("--batched", action="store_true",
                     help="also time the batched collocated apply (BP5 / BP6, 4/8/32 right-hand sides)")
+    ap.add_argument("--batched-config", type=str, default="",
+                    help="only time one batched collocated configuration p,ncomp,nrhs[,variant] at about 3e7 "
+                         "nodes per field (for profiling runs)")
     ap.add_argument("--adjoint", action="store_true",
                     help="also time the variable-coefficient forward / backward (p=4, 1e7 DOFs)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -142,6 +145,12 @@ def main():
     import paper_2109_05072_amd as mf
 
     torch.cuda.set_device(0)
+    if args.batched_config:
+        print(json.dumps(batched_one([int(v) for v in args.batched_config.split(",")], args.steps, args.warmup)),
+              flush=True)
+        if args.calib_copy:
+            calib_copy()
+        return
     orders = [int(s) for s in args.orders.split(",") if s]
     ops, xs, ys, meta = {}, {}, {}, {}
     for p in orders:
@@ -252,12 +261,7 @@ def main():
         "per_order": per_p,
     }
     if args.calib_copy:
-        a = torch.empty(1 << 27, dtype=torch.float64, device="cuda").fill_(1.0)
-        b = torch.empty_like(a)
-        for _ in range(2):
-            b.copy_(a)
-        torch.cuda.synchronize()
-        del a, b
+        calib_copy()
     for p in orders:
         ops[p].close()
     del ops, xs, ys
@@ -479,6 +483,44 @@ def batched_sweep(orders=(3, 4, 5, 6, 7, 8), dofs=3e7, ncomps=(1, 3), nrhss=(4, 
             del op
             torch.cuda.empty_cache()
     return res
+
+
+def calib_copy():
+    """Two 1 GiB device-to-device copies: a kernel of known traffic for scaling the byte counters."""
+    import torch
+    a = torch.empty(1 << 27, dtype=torch.float64, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    for _ in range(2):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    del a, b
+
+
+def batched_one(cfg, steps: int, warmup: int, dofs: float = 3e7) -> dict:
+    """One batched collocated configuration (p, ncomp, nrhs[, variant]): the default (or given) launch,
+    `steps` back-to-back applies after `warmup`, event-timed."""
+    import torch
+    import synth
+    import paper_2109_05072_amd as mf
+    p, nc, nr = cfg[:3]
+    ne = synth.elems_for_dofs(dofs, p)
+    op = mf.Operator(ne, ne, ne, p, synth.mesh_vertices(ne, ne, ne), kind="diffusion", quad="gll", ncomp=nc,
+                     dirichlet=True)
+    if len(cfg) > 3:
+        op.set_config(cfg[3], nrhs=nr)
+    x = torch.rand(op.n_nodes, nc * nr, dtype=torch.float64, device="cuda") * 2 - 1
+    y = torch.empty_like(x)
+    for _ in range(warmup):
+        op.apply(x, y)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        op.apply(x, y)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / max(steps, 1)
+    return {"p": p, "ncomp": nc, "nrhs": nr, "launch": list(op.get_config(nrhs=nr)), "ms": round(ms, 4),
+            "gdofs_fields": round(op.n_nodes * nc * nr / (ms / 1e3) / 1e9, 2)}
 
 
 def adjoint_bench(p=4, dofs=1e7):
