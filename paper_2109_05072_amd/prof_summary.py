@@ -125,53 +125,95 @@ def traffic_summary(fetch_dir: str, write_dir: str, command: str) -> str:
     return "\n".join(out) + "\n"
 
 
+_TABLE_COLS = (
+    ("waves/SIMD", "waves_per_simd", "{:.2f}"), ("valu_busy", "valu_busy", "{:.3f}"),
+    ("wait_any", "wait_any/wave", "{:.3f}"), ("wait_inst", "wait_inst_any/wave", "{:.3f}"),
+    ("wait_lds", "wait_inst_lds/wave", "{:.3f}"), ("lds_confl", "lds_conflict", "{:.3f}"),
+    ("VALU_insts", "SQ_INSTS_VALU", "{:.3e}"), ("LDS_insts", "SQ_INSTS_LDS", "{:.3e}"),
+    ("SALU_insts", "SQ_INSTS_SALU", "{:.3e}"), ("EA_RDREQ", "TCC_EA0_RDREQ_sum", "{:.3e}"),
+    ("EA_WRREQ", "TCC_EA0_WRREQ_sum", "{:.3e}"), ("L2_hit", "l2_hit", "{:.3f}"),
+)
+
+
+def _derived(m: dict) -> dict:
+    """Derived ratios from one kernel's mean counter values (see `counter_summary`)."""
+    der = {}
+    if "SQ_WAVE_CYCLES" in m and m.get("GRBM_GUI_ACTIVE", 0) > 0:
+        simd_cycles = m["GRBM_GUI_ACTIVE"] / 8 * 1024
+        der["waves_per_simd"] = 4 * m["SQ_WAVE_CYCLES"] / simd_cycles
+        if "SQ_ACTIVE_INST_VALU" in m:
+            der["valu_busy"] = 4 * m["SQ_ACTIVE_INST_VALU"] / simd_cycles
+    if m.get("SQ_WAVE_CYCLES", 0) > 0:
+        for c in ("SQ_WAIT_ANY", "SQ_WAIT_INST_ANY", "SQ_WAIT_INST_LDS"):
+            if c in m:
+                der[c.lower().replace("sq_", "") + "/wave"] = m[c] / m["SQ_WAVE_CYCLES"]
+    if "SQ_LDS_BANK_CONFLICT" in m and m.get("SQ_LDS_IDX_ACTIVE", 0) > 0:
+        der["lds_conflict"] = m["SQ_LDS_BANK_CONFLICT"] / m["SQ_LDS_IDX_ACTIVE"]
+    if m.get("TCC_HIT_sum", 0) + m.get("TCC_MISS_sum", 0) > 0:
+        der["l2_hit"] = m["TCC_HIT_sum"] / (m["TCC_HIT_sum"] + m["TCC_MISS_sum"])
+    return der
+
+
+def _counter_table(header, per_kernel: dict) -> str:
+    """One row per kernel: derived ratios and the instruction / memory-request counts behind them."""
+    w = max([len(k) for k in per_kernel] + [6])
+    out = list(header)
+    out.append(f"{'kernel':<{w}} " + " ".join(f"{c:>10}" for c, _, _ in _TABLE_COLS))
+    for k, m in per_kernel.items():
+        v = dict(m)
+        v.update(_derived(m))
+        out.append(f"{k:<{w}} " + " ".join(f"{(fmt.format(v[key]) if key in v else '-'):>10}"
+                                          for _, key, fmt in _TABLE_COLS))
+    return "\n".join(out) + "\n"
+
+
+_TABLE_NOTE = ("# derived (SQ wave-cycle counters count quad-cycles): waves/SIMD = 4*SQ_WAVE_CYCLES/(GRBM_GUI_ACTIVE/8)/1024; "
+               "valu_busy = 4*SQ_ACTIVE_INST_VALU/(GRBM_GUI_ACTIVE/8)/1024; wait_any, wait_inst, wait_lds = "
+               "SQ_WAIT_ANY, SQ_WAIT_INST_ANY, SQ_WAIT_INST_LDS per SQ_WAVE_CYCLES; lds_confl = "
+               "SQ_LDS_BANK_CONFLICT/SQ_LDS_IDX_ACTIVE; L2_hit = TCC_HIT/(TCC_HIT+TCC_MISS); instruction and "
+               "request counts are per dispatch, summed over the GPU")
+
+
 def counter_summary(dirs, command: str, sources=KERNEL_SOURCES) -> str:
-    """Per-kernel averages of every counter found in the ``--pmc`` runs under `dirs` (one directory per
-    pass), plus derived ratios where their inputs were collected:
-      waves_per_simd  = 4 SQ_WAVE_CYCLES / (GRBM_GUI_ACTIVE / 8 XCDs) / 1024 SIMDs  (mean resident waves;
-                        the SQ wave-cycle counters count quad-cycles, GRBM_GUI_ACTIVE single cycles summed
-                        over the 8 XCDs)
-      valu_busy       = 4 SQ_ACTIVE_INST_VALU / (GRBM_GUI_ACTIVE / 8) / 1024  (share of SIMD cycles issuing
-                        VALU instructions)
-      wait_any/wave   = SQ_WAIT_ANY / SQ_WAVE_CYCLES, wait_inst_any/wave = SQ_WAIT_INST_ANY / SQ_WAVE_CYCLES
-                        (shares of a wave's resident cycles; same unit on both sides)
-      lds_conflict    = SQ_LDS_BANK_CONFLICT / SQ_LDS_IDX_ACTIVE
+    """Per-kernel averages of the counters found in the ``--pmc`` runs under `dirs` (one directory per
+    pass), as a table of derived ratios where their inputs were collected:
+      waves/SIMD  = 4 SQ_WAVE_CYCLES / (GRBM_GUI_ACTIVE / 8 XCDs) / 1024 SIMDs  (mean resident waves; the SQ
+                    wave-cycle counters count quad-cycles, GRBM_GUI_ACTIVE single cycles summed over the 8 XCDs)
+      valu_busy   = 4 SQ_ACTIVE_INST_VALU / (GRBM_GUI_ACTIVE / 8) / 1024  (share of SIMD cycles issuing VALU)
+      wait_*      = SQ_WAIT_ANY, SQ_WAIT_INST_ANY, SQ_WAIT_INST_LDS over SQ_WAVE_CYCLES (same unit both sides)
+      lds_confl   = SQ_LDS_BANK_CONFLICT / SQ_LDS_IDX_ACTIVE, L2_hit = TCC_HIT / (TCC_HIT + TCC_MISS)
     Counter values are per dispatch, summed over the GPU by rocprofv3."""
     vals = defaultdict(lambda: defaultdict(list))
     for d in dirs:
         for r in csv.DictReader(open(_find(d, "counter_collection.csv"))):
             vals[r["Kernel_Name"]][r["Counter_Name"]].append(float(r["Counter_Value"]))
-    names = sorted({c for k in vals for c in vals[k]})
-    out = [f"# rocprofv3 counters per dispatch (mean over dispatches)", f"# command: {command}",
-           f"# kernel source hash: {kernel_source_hash(sources)}",
-           "# derived (SQ wave-cycle counters count quad-cycles): waves_per_simd = "
-           "4*SQ_WAVE_CYCLES/(GRBM_GUI_ACTIVE/8)/1024; valu_busy = 4*SQ_ACTIVE_INST_VALU/(GRBM_GUI_ACTIVE/8)/1024; "
-           "wait ratios per wave cycle; lds_conflict = SQ_LDS_BANK_CONFLICT/SQ_LDS_IDX_ACTIVE"]
+    per = {}
     for k in vals:
         sk = _short(k)
-        if not (sk.startswith("k_apply") or sk.startswith("k_mass") or sk.startswith("k_tet")):
+        if sk.startswith("k_apply") or sk.startswith("k_mass") or sk.startswith("k_tet"):
+            per[sk] = {c: sum(v) / len(v) for c, v in vals[k].items()}
+    header = [f"# rocprofv3 counters per dispatch (mean over dispatches)", f"# command: {command}",
+              f"# kernel source hash: {kernel_source_hash(sources)}", _TABLE_NOTE]
+    return _counter_table(header, per)
+
+
+def condense(path: str) -> str:
+    """Rewrite a per-counter listing (one block per kernel, one ``COUNTER value`` line each) as the table
+    `counter_summary` prints, keeping the listing's header lines."""
+    header, per, cur = [], {}, None
+    for line in open(path).read().splitlines():
+        if line.startswith("#"):
+            if not line.startswith("# derived"):
+                header.append(line)
+        elif line.startswith("    = "):
             continue
-        m = {c: sum(v) / len(v) for c, v in vals[k].items()}
-        out.append(f"{sk}")
-        for c in names:
-            if c in m:
-                out.append(f"    {c:<28} {m[c]:.4g}")
-        der = {}
-        if "SQ_WAVE_CYCLES" in m and "GRBM_GUI_ACTIVE" in m and m["GRBM_GUI_ACTIVE"] > 0:
-            simd_cycles = m["GRBM_GUI_ACTIVE"] / 8 * 1024
-            der["waves_per_simd"] = 4 * m["SQ_WAVE_CYCLES"] / simd_cycles
-            if "SQ_ACTIVE_INST_VALU" in m:
-                der["valu_busy"] = 4 * m["SQ_ACTIVE_INST_VALU"] / simd_cycles
-        if "SQ_WAVE_CYCLES" in m and m["SQ_WAVE_CYCLES"] > 0:
-            for c in ("SQ_WAIT_ANY", "SQ_WAIT_INST_ANY", "SQ_WAIT_INST_LDS", "SQ_ACTIVE_INST_LDS",
-                      "SQ_ACTIVE_INST_SCA", "SQ_ACTIVE_INST_VMEM", "SQ_ACTIVE_INST_VALU"):
-                if c in m:
-                    der[c.lower().replace("sq_", "") + "/wave"] = m[c] / m["SQ_WAVE_CYCLES"]
-        if "SQ_LDS_BANK_CONFLICT" in m and m.get("SQ_LDS_IDX_ACTIVE", 0) > 0:
-            der["lds_conflict"] = m["SQ_LDS_BANK_CONFLICT"] / m["SQ_LDS_IDX_ACTIVE"]
-        for c, v in der.items():
-            out.append(f"    = {c:<26} {v:.4f}")
-    return "\n".join(out) + "\n"
+        elif line.startswith("    "):
+            c, v = line.split()
+            per[cur][c] = float(v)
+        elif line.strip():
+            cur = line.strip()
+            per[cur] = {}
+    return _counter_table(header + [_TABLE_NOTE], per)
 
 
 def read_traffic(path: str):
@@ -200,6 +242,8 @@ if __name__ == "__main__":
     elif mode == "counters":
         # counters <dir1,dir2,...> <cmd...>
         sys.stdout.write(counter_summary(sys.argv[2].split(","), " ".join(sys.argv[3:])))
+    elif mode == "condense":
+        sys.stdout.write(condense(sys.argv[2]))
     elif mode == "traffic":
         sys.stdout.write(traffic_summary(sys.argv[2], sys.argv[3], " ".join(sys.argv[4:])))
     else:
