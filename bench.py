@@ -228,9 +228,14 @@ def main():
     if args.kind == "diffusion":
         tag = "otf " if args.otf else ""
         traffic = read_traffic(os.path.join(ROOT, "profiles", f"bp3{'_otf' if args.otf else ''}_apply_traffic.txt"))
-        kname = "k_apply_gf" if lg["variant"] >= 9 else "k_apply"
+        gf = 9 <= lg["variant"] <= 14
+        kname = "k_apply_gf" if gf else "k_apply"
+        # the launch variants that load the factors in the pointwise stage (points per batch), as the
+        # profile summaries name their kernels
+        late = {(7, 2): 2, (8, 4): 2, (9, 2): 2, (10, 2): 4}.get((dom["p"] + 2, lg["variant"]))
+        suffix = " late-factors" if lg["variant"] == 14 else f" late{late}" if late and not args.otf else ""
         dom_name = (f"{kname} p={dom['p']} q={dom['p'] + 2} diffusion {tag}double G={lg['elements_per_group']} "
-                    f"NT={lg['threads_per_group']}{' late-factors' if lg['variant'] == 14 else ''}")
+                    f"NT={lg['threads_per_group']}{suffix}")
     else:
         traffic = read_traffic(os.path.join(ROOT, "profiles", "bp1_apply_traffic.txt"))
         dom_name = (f"k_mass p={dom['p']} q={dom['p'] + 2} double G={lg['elements_per_group']} "
@@ -410,7 +415,7 @@ def sweep_variants(op, x, p, reps=10, rounds=3, nrhs=1):
     default = op.get_config(nrhs=nrhs)
     depths = (1, 2, 4) if op.kind == "mass" else (1,)
     cfgs = []
-    for v in range(15):
+    for v in range(17):
         for d in depths:
             try:
                 op.set_config(v, nrhs=nrhs, groups_per_block=d)

@@ -318,11 +318,13 @@ int mfhex_tune(mfhex_op op, int prec, int nrhs, void *scratch_dev, const char *c
 int mfhex_get_config(mfhex_op op, int prec, int nrhs, int32_t *variant, int32_t *elems_per_group,
                      int32_t *threads_per_group, int32_t *groups_per_block);
 
-/* Force the launch configuration for (prec, nrhs): variant 0 .. 14 (5 .. 8
+/* Force the launch configuration for (prec, nrhs): variant 0 .. 16 (5 .. 8
  * carry 2, 4, 8, 16 vectors of a multi-vector together; 9 .. 14 are the
  * factored-gradient diffusion kernel for Gauss points, which forms the
  * gradient with the basis derivative at the points in three contraction
- * stages instead of six) and pipeline depth
+ * stages instead of six; 15 and 16 carry 4 and 8 vectors with the gradient
+ * contractions on the FP64 matrix cores, collocated FP64 diffusion only) and
+ * pipeline depth
  * groups_per_block (0: the operator's default, measured per order for mass
  * and 1 for diffusion; mass accepts 1 .. 64, diffusion only 1).
  * MFHEX_ERR_ARG if out of range. */

@@ -444,6 +444,87 @@ __device__ __forceinline__ void grad(T *s0, T *s1, T *s2, const T *__restrict__ 
     group_sync<NT>();
 }
 
+// Matrix-core form of the collocated gradient's contractions (Sec. 2.2 puts
+// the tensor contractions of a batch of elements on batched small GEMMs).
+// Each contraction is a product C = M S of the Q x Q matrix M (D or D^T) with
+// S = [Q x lines], 16 lines at a time on the FP64 16x16x4 matrix instruction:
+// A = M padded to 16 rows, K = Q in steps of 4 (zero-padded), B = the 4 x 16
+// slice of the lines' values.  Lane l holds A[l % 16][4s + l / 16] and
+// B[4s + l / 16][l % 16] for step s, and result register r holds
+// C[4r + l / 16][l % 16].  The product runs on the unfolded matrix: the matrix
+// cores cannot use the even-odd folding, so they issue 16/Q times (rows) and
+// 4 ceil(Q/4)/Q times (depth) the products the folded VALU form needs.
+constexpr int mx_steps(int Q) { return (Q + 3) / 4; }
+
+// A-operand fragments of the unfolded matrix M, rebuilt from its folded rows
+// (see contract): M[o][i] = Me[o][i] + Mo[o][i], M[o][Q-1-i] = Me[o][i] -
+// Mo[o][i] (i < Q/2), M[o][mid] = the middle coefficient, for o < ceil(Q/2);
+// M[Q-1-o][Q-1-i] = SYM M[o][i].
+template <int Q, int SYM>
+__device__ __forceinline__ void mx_fragments(const double *__restrict__ MF, double (&a)[mx_steps(Q)], int lane)
+{
+    constexpr int H = Q / 2, NOH = (Q + 1) / 2;
+    const int o = lane & 15, kq = lane >> 4;
+#pragma unroll
+    for (int s = 0; s < mx_steps(Q); ++s) {
+        const int i = 4 * s + kq;
+        double m = 0.0;
+        if (o < Q && i < Q) {
+            const bool top = o < NOH;
+            const int oo = top ? o : Q - 1 - o, ii = top ? i : Q - 1 - i;
+            const double *row = MF + oo * Q;
+            double v;
+            if ((Q & 1) && ii == H) v = row[2 * H];
+            else if (ii < H) v = row[ii] + row[H + ii];
+            else v = row[Q - 1 - ii] - row[H + Q - 1 - ii];
+            m = top ? v : SYM * v;
+        }
+        a[s] = m;
+    }
+}
+
+// Contract axis AX of the GV cubes Q^3 (same lines and LDS layout as
+// contract): dst = M src (+ a1 + a2 with ADD2), in place allowed.  The tiles
+// of 16 lines are dealt to the wavefronts of the group; a wavefront reads all
+// values of its tile before it writes any, and no two tiles share a line.
+template <int AX, int Q, int GV, int NT, bool ADD2 = false>
+__device__ __forceinline__ void contract_mx(const double *src, double *dst, const double (&a)[mx_steps(Q)], int tid,
+                                            const double *a1 = nullptr, const double *a2 = nullptr)
+{
+    typedef double d4 __attribute__((ext_vector_type(4)));
+    using L = Lds<Q>;
+    constexpr int SA = AX == 0 ? L::PITCH : 1;
+    constexpr int SB = AX == 2 ? L::PITCH : L::PLANE;
+    constexpr int ST = AX == 0 ? 1 : AX == 1 ? L::PITCH : L::PLANE;
+    constexpr int NPEN = GV * Q * Q, NTILE = (NPEN + 15) / 16, NW = NT / 64;
+    static_assert(NT % 64 == 0 && Q <= 16, "whole wavefronts, at most 16 rows");
+    const int lane = tid & 63, w = tid >> 6;
+    const int col = lane & 15, kq = lane >> 4;
+    for (int t = w; t < NTILE; t += NW) {
+        const int id = t * 16 + col;
+        const bool ok = id < NPEN;
+        const int idc = ok ? id : 0;
+        const int la = idc % Q, tt = idc / Q, lb = tt % Q, g = tt / Q;
+        const int base = g * L::BUF + la * SA + lb * SB;
+        d4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int s = 0; s < mx_steps(Q); ++s) {
+            const int i = 4 * s + kq;
+            const double b = i < Q ? src[base + (i < Q ? i : 0) * ST] : 0.0;
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s], b, acc, 0, 0, 0);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int o = 4 * r + kq;
+            if (ok && o < Q) {
+                double v = acc[r];
+                if constexpr (ADD2) v += a1[base + o * ST] + a2[base + o * ST];
+                dst[base + o * ST] = v;
+            }
+        }
+    }
+}
+
 // One contraction shared by the two halves of a split group (one element,
 // NT2 threads per half, every line owned by one lane of each half): half 0
 // forms output pairs o < OM, half 1 the rest.
@@ -471,7 +552,7 @@ __device__ __forceinline__ void contract_halves(const T *src, T *dst, const T *_
 // registers (the same expressions as the set-up kernel), instead of reading
 // six factors per point from HBM.
 template <int P, int Q, bool COLLOC, int MODE, bool VARK, typename T, int G, int NT, int VC, bool OTF, bool DET,
-          bool STAGE = false, int LATE = 0>
+          bool STAGE = false, int LATE = 0, bool MX = false>
 __global__ void __launch_bounds__(NT)
 k_apply(const T *__restrict__ bas, const int nex, const int ney, const int nvec, const int32_t *__restrict__ offsets,
         const T *__restrict__ qdata, const double *__restrict__ kappa, const double *__restrict__ wdet,
@@ -505,6 +586,13 @@ k_apply(const T *__restrict__ bas, const int nex, const int ney, const int nvec,
     const GroupPos gpos = group_pos<G>(xcd_block(blockIdx.x, gridDim.x), nex);
     const int64_t e0 = gpos.e0;
     const int nvalid = gpos.nvalid;
+    // MX: the collocated gradient and its transpose on the matrix cores (fragments of D and D^T)
+    static_assert(!MX || (COLLOC && MODE == kDiff && !SPLIT && !OTF && sizeof(T) == 8), "matrix-core stages");
+    double mxd[MX ? mx_steps(Q) : 1], mxt[MX ? mx_steps(Q) : 1];
+    if constexpr (MX) {
+        mx_fragments<Q, -1>(reinterpret_cast<const double *>(bas) + basis_df(P, Q), mxd, tid & 63);
+        mx_fragments<Q, -1>(reinterpret_cast<const double *>(bas) + basis_dtf(P, Q), mxt, tid & 63);
+    }
     if constexpr (STAGE) {
         static_assert(G == 1 && !SPLIT && !OTF, "staged scatter: one element, plain stages");
         for (int t = tid; t < P3; t += NT) soff[t] = __builtin_nontemporal_load(&offsets[e0 * P3 + t]);
@@ -632,6 +720,13 @@ k_apply(const T *__restrict__ bas, const int nex, const int ney, const int nvec,
                                                                                      lane);
                 }
                 group_sync<NT>();
+            } else if constexpr (MX) {
+                double *const d0 = reinterpret_cast<double *>(s0);
+                contract_mx<0, Q, GV, NT>(d0, reinterpret_cast<double *>(s1), mxd, tid);
+                contract_mx<1, Q, GV, NT>(d0, reinterpret_cast<double *>(s2), mxd, tid);
+                group_sync<NT>();
+                contract_mx<2, Q, GV, NT>(d0, d0, mxd, tid);
+                group_sync<NT>();
             } else {
                 interp<P, Q, COLLOC, GV, NT, T>(s0, bas, tid);
                 grad<P, Q, GV, NT, T>(s0, s1, s2, bas, tid);
@@ -693,14 +788,23 @@ k_apply(const T *__restrict__ bas, const int nex, const int ney, const int nvec,
                 } else {
                     // transposed gradient: x and y lines in place, then the z lines
                     // of s0 with the x and y parts added
-                    if constexpr (fuse_xy(Q, GV, NT)) {
+                    if constexpr (MX) {
+                        double *const d1 = reinterpret_cast<double *>(s1), *const d2 = reinterpret_cast<double *>(s2);
+                        contract_mx<0, Q, GV, NT>(d1, d1, mxt, tid);
+                        contract_mx<1, Q, GV, NT>(d2, d2, mxt, tid);
+                    } else if constexpr (fuse_xy(Q, GV, NT)) {
                         contract_xy<Q, GV, NT, -1>(s1, s1, s2, s2, bas + basis_dtf(P, Q), tid);
                     } else {
                         contract<0, Q, Q, Q, Q, GV, NT, Q, -1>(s1, s1, bas + basis_dtf(P, Q), tid);
                         contract<1, Q, Q, Q, Q, GV, NT, Q, -1>(s2, s2, bas + basis_dtf(P, Q), tid);
                     }
                     group_sync<NT>();
-                    contract<2, Q, Q, Q, Q, GV, NT, Q, -1, T, true>(s0, s0, bas + basis_dtf(P, Q), tid, s1, s2);
+                    if constexpr (MX)
+                        contract_mx<2, Q, GV, NT, true>(reinterpret_cast<double *>(s0), reinterpret_cast<double *>(s0),
+                                                        mxt, tid, reinterpret_cast<const double *>(s1),
+                                                        reinterpret_cast<const double *>(s2));
+                    else
+                        contract<2, Q, Q, Q, Q, GV, NT, Q, -1, T, true>(s0, s0, bas + basis_dtf(P, Q), tid, s1, s2);
                     // same lines, same lanes: B^T along z follows without a sync
                 }
             }
@@ -1302,8 +1406,11 @@ static hipError_t launch_apply_v(const ApplyLaunch &a)
 {
     constexpr int G = variant_g(Q, V, MODE), NT = variant_nt(Q, V), VC = variant_vc(V);
     constexpr size_t lds = apply_lds(P, Q, MODE, sizeof(T), V, OTF);
+    // matrix-core gradient: collocated FP64 diffusion with stored factors
+    constexpr bool MX = variant_mx(V);
+    constexpr bool mx_ok = COLLOC && MODE == kDiff && sizeof(T) == 8 && !OTF && !VARK;
     // chunked multi-vector variants exist for the plain mass / diffusion operators only
-    if constexpr ((VC > 1 && (MODE == kRhs || VARK || OTF)) || lds > kMaxLds) {
+    if constexpr ((VC > 1 && (MODE == kRhs || VARK || OTF)) || lds > kMaxLds || (MX && !mx_ok)) {
         (void)a;
         return hipErrorInvalidValue;
     } else if constexpr (MODE == kMass) {
@@ -1332,11 +1439,12 @@ static hipError_t launch_apply_v(const ApplyLaunch &a)
         if constexpr (staged_scatter(MODE, VC, sizeof(T)) && !DET && !VARK && !OTF) {
             constexpr size_t lds_st = apply_lds(P, Q, MODE, sizeof(T), V, OTF, true);
             if constexpr (lds_st <= kMaxLds) {
-                if (a.nvec > VC) return go(k_apply<P, Q, COLLOC, MODE, VARK, T, G, NT, VC, OTF, DET, true>, lds_st);
+                if (a.nvec > VC)
+                    return go(k_apply<P, Q, COLLOC, MODE, VARK, T, G, NT, VC, OTF, DET, true, 0, MX>, lds_st);
             }
         }
         constexpr int LATE = MODE == kDiff && VC == 1 && !OTF ? variant_late(Q, V) : 0;
-        return go(k_apply<P, Q, COLLOC, MODE, VARK, T, G, NT, VC, OTF, DET, false, LATE>, lds);
+        return go(k_apply<P, Q, COLLOC, MODE, VARK, T, G, NT, VC, OTF, DET, false, LATE, MX>, lds);
     }
 }
 
@@ -1387,6 +1495,8 @@ static hipError_t launch_apply_vd(const ApplyLaunch &a)
     case 5: return launch_apply_v<P, Q, COLLOC, MODE, VARK, T, 5, OTF, DET>(a);
     case 6: return launch_apply_v<P, Q, COLLOC, MODE, VARK, T, 6, OTF, DET>(a);
     case 7: return launch_apply_v<P, Q, COLLOC, MODE, VARK, T, 7, OTF, DET>(a);
+    case 15: return launch_apply_v<P, Q, COLLOC, MODE, VARK, T, 15, OTF, DET>(a);
+    case 16: return launch_apply_v<P, Q, COLLOC, MODE, VARK, T, 16, OTF, DET>(a);
     default: return hipErrorInvalidValue;
     }
 }

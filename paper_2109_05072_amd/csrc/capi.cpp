@@ -163,6 +163,8 @@ bool valid_variant(const mfhex_op_s &op, int prec, int variant)
     if (otf && variant_vc(variant) > 1) return false;  // in-kernel factors: single-vector variants
     // the factored-gradient kernel: diffusion with Gauss points and stored factors
     if (variant_gf(variant) && (mode_of(op) != kDiff || op.basis.colloc || otf)) return false;
+    // the matrix-core gradient: collocated FP64 diffusion with stored factors
+    if (variant_mx(variant) && (mode_of(op) != kDiff || !op.basis.colloc || otf || prec != MFHEX_F64)) return false;
     return apply_lds(op.P, op.Q, mode_of(op), prec == MFHEX_F32 ? 4 : 8, variant, otf) <= kMaxLds;
 }
 

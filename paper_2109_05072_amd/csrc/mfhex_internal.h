@@ -115,29 +115,39 @@ constexpr bool split_stages(int Q, int mode, int G, int NT, int VC)
 // .. 10; variant 0 is the measured best on MI355X for one vector); variants
 // 5..8 carry a chunk of VC = 2, 4, 8, 16 vectors of a multi-vector together
 // (one element per group), sharing the geometric factors and reading /
-// writing each node's chunk as one contiguous run.
-constexpr int kNumVariants = 15;
+// writing each node's chunk as one contiguous run.  Variants 9..14 are the
+// factored-gradient kernel (below); 15 and 16 are chunks of 4 and 8 vectors
+// whose collocated gradient contractions run on the FP64 matrix cores.
+constexpr int kNumVariants = 17;
 // At q = 6 and 7 variant 4 fills the lanes: every contraction of the diffusion
 // kernel runs over G q^2 lines (q^2 = 36, 49), so 7 and 5 elements per
 // 256-thread group give 252 and 245 lines, where groups of 1 or 2 elements
 // leave 44-62% of the lanes idle.
-// At q = 10 variant 2 loads each point's geometric factors in the pointwise stage (four points
-// at a time) instead of at the start of the element group: the prefetched factors of 8 points per
-// lane take 96 registers, so without them a 128-thread group fits five waves per SIMD instead of
-// two.  Measured against variant 0 it was 6% faster on one box and 5% slower on another, so it
-// is a tuner candidate, not the default.
+// Late factor loads: at q = 7 and 9 variant 2 and at q = 8 and 10 variants 4 and 2 load each
+// point's geometric factors in the pointwise stage (the listed number of points at a time)
+// instead of at the start of the element group.  The prefetched factors of a lane's points hold
+// 6 x 2 registers per point (8 points per lane at q = 10 with 128 threads: 96 registers) through
+// every forward contraction; loaded late they are live in the pointwise stage only, so more
+// wavefronts fit on a SIMD (q = 7..9, two points at a time: 64-72 registers instead of 120-142)
+// while the loads' latency is no longer hidden by the contractions.  At q = 10 this was 6% faster
+// on one box and 5% slower on another against variant 0, so these are tuner candidates, not
+// defaults.
 constexpr int kVarG[9][5] = {
     {16, 8, 32, 16, 32}, {8, 4, 16, 8, 16}, {4, 2, 8, 4, 8}, {4, 2, 8, 2, 8}, {1, 2, 1, 2, 7},
-    {1, 2, 1, 1, 5},     {1, 1, 1, 2, 2},   {2, 1, 1, 1, 2}, {1, 1, 1, 2, 2}};
+    {1, 2, 1, 1, 5},     {1, 1, 1, 2, 1},   {2, 1, 1, 1, 2}, {1, 1, 1, 2, 2}};
 constexpr int kVarNT[9][5] = {
     {64, 64, 64, 128, 128},  {64, 64, 64, 128, 128},  {64, 64, 64, 128, 128},
-    {128, 64, 128, 128, 256}, {64, 64, 128, 128, 256}, {64, 128, 128, 256, 256},
-    {128, 256, 64, 128, 64}, {256, 128, 64, 256, 256}, {256, 128, 128, 128, 256}};
+    {128, 64, 128, 128, 256}, {64, 64, 128, 128, 256}, {64, 128, 64, 256, 256},
+    {128, 256, 64, 128, 128}, {256, 128, 128, 256, 256}, {256, 128, 128, 128, 256}};
 // points per factor-load batch in the pointwise stage (0: factors prefetched at the group start)
 constexpr int kVarLate[9][5] = {{0, 0, 0, 0, 0}, {0, 0, 0, 0, 0}, {0, 0, 0, 0, 0}, {0, 0, 0, 0, 0}, {0, 0, 0, 0, 0},
-                                {0, 0, 0, 0, 0}, {0, 0, 0, 0, 0}, {0, 0, 0, 0, 0}, {0, 0, 4, 0, 0}};
+                                {0, 0, 2, 0, 0}, {0, 0, 0, 0, 2}, {0, 0, 2, 0, 0}, {0, 0, 4, 0, 0}};
 constexpr int variant_late(int Q, int v) { return v < 5 ? kVarLate[Q - 2][v] : 0; }
-constexpr int variant_vc(int v) { return v < 5 || v >= 9 ? 1 : v == 5 ? 2 : v == 6 ? 4 : v == 7 ? 8 : 16; }
+constexpr bool variant_mx(int v) { return v >= 15; }
+constexpr int variant_vc(int v)
+{
+    return v == 15 ? 4 : v == 16 ? 8 : v < 5 || v >= 9 ? 1 : v == 5 ? 2 : v == 6 ? 4 : v == 7 ? 8 : 16;
+}
 // Variants 9 .. 14: the factored-gradient diffusion kernel (Gauss points, one vector at a time;
 // k_apply_gf): 9 .. 13 take the (elements, threads) pairs below per q and load the geometric
 // factors at the start of the element group; 14 is variant 9 loading them in the middle of the
@@ -148,7 +158,7 @@ constexpr int kGfG[9][5] = {{16, 8, 32, 16, 8}, {16, 8, 32, 16, 8}, {8, 4, 16, 8
 constexpr int kGfNT[9][5] = {{128, 64, 256, 256, 128}, {128, 64, 256, 256, 128}, {128, 64, 256, 256, 128},
                              {256, 128, 64, 128, 64},  {128, 64, 256, 256, 128}, {128, 64, 256, 64, 128},
                              {64, 128, 256, 128, 64},  {128, 64, 256, 128, 256}, {128, 64, 256, 128, 256}};
-constexpr bool variant_gf(int v) { return v >= 9; }
+constexpr bool variant_gf(int v) { return v >= 9 && v <= 14; }
 constexpr bool gf_prefetch(int v) { return v != 14; }
 constexpr int gf_slot(int v) { return v == 14 ? 0 : v - 9; }
 // The mass operator keeps one LDS array per element instead of three and has

@@ -40,17 +40,18 @@ def kernel_source_hash(sources=KERNEL_SOURCES) -> str:
 
 def _short(name: str) -> str:
     m = re.match(r"void mfhex::k_apply<(\d+), (\d+), (\w+), (\d), (\w+), (\w+), (\d+), (\d+)(?:, (\d+))?"
-                 r"(?:, (true|false))?(?:, (true|false))?(?:, (true|false))?(?:, (\d+))?>", name)
+                 r"(?:, (true|false))?(?:, (true|false))?(?:, (true|false))?(?:, (\d+))?(?:, (true|false))?>", name)
     if m:
-        P, Q, colloc, mode, vark, T, G, NT, VC, otf, det, stage, late = m.groups()
+        P, Q, colloc, mode, vark, T, G, NT, VC, otf, det, stage, late, mx = m.groups()
         kind = {"0": "mass", "1": "diffusion", "2": "rhs"}[mode]
         vc = f" VC={VC}" if VC and VC != "1" else ""
         geo = " otf" if otf == "true" else ""
         dt = " det" if det == "true" else ""
         st = " staged" if stage == "true" else ""
         lt = f" late{late}" if late and late != "0" else ""
+        mc = " mfma" if mx == "true" else ""
         return (f"k_apply p={int(P) - 1} q={Q} {kind}{' kappa' if vark == 'true' else ''}{geo} {T} G={G} NT={NT}"
-                f"{vc}{dt}{st}{lt}")
+                f"{vc}{dt}{st}{lt}{mc}")
     m = re.match(r"void mfhex::k_apply_gf<(\d+), (\d+), (\w+), (\w+), (\d+), (\d+), (\w+)(?:, (true|false))?>", name)
     if m:
         P, Q, vark, T, G, NT, pf, det = m.groups()

@@ -60,7 +60,7 @@ def valid_variants(op, dtype=torch.float64, nrhs=1):
     """Launch variants the operator accepts (some exceed the LDS budget at high order)."""
     from paper_2109_05072_amd import _lib as L
     out = []
-    for v in range(15):
+    for v in range(17):
         try:
             op.set_config(v, dtype, nrhs)
             out.append(v)
@@ -326,7 +326,7 @@ def test_every_launch_configuration_agrees(gpu_lib, p, quad, nrhs):
         op.set_config(v, nrhs=nrhs)
         assert relerr(host(op.apply(x)), ref) <= 1e-13
     with pytest.raises(L.MFHexError):
-        op.set_config(15, nrhs=nrhs)  # one past the last variant
+        op.set_config(17, nrhs=nrhs)  # one past the last variant
     best = op.tune(nrhs=nrhs)
     assert best[0] in vs and best[3] == 1
     assert relerr(host(op.apply(x)), ref) <= 1e-13
