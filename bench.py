@@ -230,9 +230,7 @@ def main():
         traffic = read_traffic(os.path.join(ROOT, "profiles", f"bp3{'_otf' if args.otf else ''}_apply_traffic.txt"))
         gf = 9 <= lg["variant"] <= 14
         kname = "k_apply_gf" if gf else "k_apply"
-        # the launch variants that load the factors in the pointwise stage (points per batch), as the
-        # profile summaries name their kernels
-        late = {(7, 2): 2, (8, 4): 2, (9, 2): 2, (10, 2): 4}.get((dom["p"] + 2, lg["variant"]))
+        late = LATE_FACTOR_SLOTS.get((dom["p"] + 2, lg["variant"]))
         suffix = " late-factors" if lg["variant"] == 14 else f" late{late}" if late and not args.otf else ""
         dom_name = (f"{kname} p={dom['p']} q={dom['p'] + 2} diffusion {tag}double G={lg['elements_per_group']} "
                     f"NT={lg['threads_per_group']}{suffix}")
@@ -294,6 +292,12 @@ def main():
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(dom["p"])
     print(json.dumps(out), flush=True)
+
+
+# (q, variant) -> points per factor-load batch of the launch variants that load the geometric
+# factors in the pointwise stage (kVarLate in csrc/mfhex_internal.h), so that the dominant kernel
+# is named as the profile summaries name it
+LATE_FACTOR_SLOTS = {(7, 2): 2, (8, 4): 2, (9, 2): 2, (9, 4): 2, (10, 2): 4, (10, 3): 2}
 
 
 def measure_copy_gbs(nbytes: int = 1 << 30, reps: int = 5) -> float:

@@ -92,8 +92,11 @@ struct KgradLaunch {
 };
 
 // LDS layout of one element's working array: [c][b][a] with an odd row pitch so
-// that pencils along any axis hit distinct banks.
-constexpr int lds_pitch(int Q) { return (Q % 2 == 0) ? Q + 1 : Q; }
+// that pencils along any axis hit distinct banks; q = 10 keeps the pitch of 10,
+// which fits a split group's four arrays in 32 KB, five groups per CU (4% faster
+// than pitch 11 for the prefetching split group in same-box A/B, where the
+// padding left room for four).
+constexpr int lds_pitch(int Q) { return (Q % 2 == 0 && Q != 10) ? Q + 1 : Q; }
 constexpr int lds_buf(int Q) { return lds_pitch(Q) * Q * Q; }
 constexpr int apply_nbuf(int mode, bool split = false) { return mode == 1 ? (split ? 4 : 3) : 1; }
 // Split stages of the diffusion kernel: with one element and one vector per
@@ -130,18 +133,21 @@ constexpr int kNumVariants = 17;
 // every forward contraction; loaded late they are live in the pointwise stage only, so more
 // wavefronts fit on a SIMD (q = 7..9, two points at a time: 64-72 registers instead of 120-142)
 // while the loads' latency is no longer hidden by the contractions.  At q = 10 this was 6% faster
-// on one box and 5% slower on another against variant 0, so these are tuner candidates, not
-// defaults.
+// on one box and 5% slower on another against variant 0 with 128 threads.  With 256 threads
+// (split stages) the late loads are the q = 9 and 10 defaults: 68 and 81 registers instead of 101
+// and 126, so that five to six groups fit per CU (at q = 10 with the unpadded row pitch, which
+// puts the four arrays of a group in 32 KB); same-box A/B, one element per group: q = 9 6%
+// faster than the best prefetching variant, q = 10 11%.
 constexpr int kVarG[9][5] = {
     {16, 8, 32, 16, 32}, {8, 4, 16, 8, 16}, {4, 2, 8, 4, 8}, {4, 2, 8, 2, 8}, {1, 2, 1, 2, 7},
-    {1, 2, 1, 1, 5},     {1, 1, 1, 2, 1},   {2, 1, 1, 1, 2}, {1, 1, 1, 2, 2}};
+    {1, 2, 1, 1, 5},     {1, 1, 1, 2, 1},   {2, 1, 1, 1, 1}, {1, 1, 1, 1, 2}};
 constexpr int kVarNT[9][5] = {
     {64, 64, 64, 128, 128},  {64, 64, 64, 128, 128},  {64, 64, 64, 128, 128},
     {128, 64, 128, 128, 256}, {64, 64, 128, 128, 256}, {64, 128, 64, 256, 256},
-    {128, 256, 64, 128, 128}, {256, 128, 128, 256, 256}, {256, 128, 128, 128, 256}};
+    {128, 256, 64, 128, 128}, {256, 128, 128, 256, 256}, {256, 128, 128, 256, 256}};
 // points per factor-load batch in the pointwise stage (0: factors prefetched at the group start)
 constexpr int kVarLate[9][5] = {{0, 0, 0, 0, 0}, {0, 0, 0, 0, 0}, {0, 0, 0, 0, 0}, {0, 0, 0, 0, 0}, {0, 0, 0, 0, 0},
-                                {0, 0, 2, 0, 0}, {0, 0, 0, 0, 2}, {0, 0, 2, 0, 0}, {0, 0, 4, 0, 0}};
+                                {0, 0, 2, 0, 0}, {0, 0, 0, 0, 2}, {0, 0, 2, 0, 2}, {0, 0, 4, 2, 0}};
 constexpr int variant_late(int Q, int v) { return v < 5 ? kVarLate[Q - 2][v] : 0; }
 constexpr bool variant_mx(int v) { return v >= 15; }
 constexpr int variant_vc(int v)
@@ -214,12 +220,13 @@ constexpr size_t kLdsTwoGroups = 81920;  // at most this much LDS leaves room fo
 // mass operator, the pipeline depth measured fastest (median of interleaved
 // timings at about 1e7 DOFs on perturbed box meshes, Gauss q = p+2); orders
 // not measured there keep variant 0.
-constexpr int kDefVariantDiff[9] = {0, 0, 0, 4, 4, 4, 0, 1, 0};
+constexpr int kDefVariantDiff[9] = {0, 0, 0, 4, 4, 4, 0, 4, 3};
 // FP32 diffusion (the operator inside mixed-precision CG): half the register and LDS footprint
 // favours two-element groups at q = 8 (20-27% faster than the FP64 choice at 1e7 and 3e7 nodes);
 // the lane-filling groups of q = 6 and 7 are 6% and 6-12% faster than the earlier two-element
-// choices; at q = 9 the best choice changes with the mesh size, and it and the other q keep the
-// FP64 choice.
+// choices; at q = 9 the best choice changes with the mesh size; q = 9 and 10 keep the one-element
+// groups that prefetch their factors (the late-factor groups that are the FP64 defaults there
+// were measured in FP64 only).
 constexpr int kDefVariantDiff32[9] = {0, 0, 0, 4, 4, 4, 3, 1, 0};
 constexpr int kDefVariantMass[9] = {0, 0, 0, 3, 3, 1, 3, 0, 4};
 constexpr int kDefChainMass[9] = {2, 2, 2, 4, 2, 4, 4, 4, 2};
