@@ -525,18 +525,18 @@ __device__ __forceinline__ void contract_mx(const double *src, double *dst, cons
     }
 }
 
-// One contraction shared by the two halves of a split group (one element,
+// One contraction shared by the two halves of a split group (G elements,
 // NT2 threads per half, every line owned by one lane of each half): half 0
 // forms output pairs o < OM, half 1 the rest.
-template <int AX, int E0, int E1, int E2, int NO, int NT2, int Q, int SYM, typename T, bool ADD2 = false,
+template <int AX, int E0, int E1, int E2, int NO, int G, int NT2, int Q, int SYM, typename T, bool ADD2 = false,
           int OM = ((NO + 1) / 2 + 1) / 2>
 __device__ __forceinline__ void contract_halves(const T *src, T *dst, const T *__restrict__ MF, int half, int lane,
                                                 const T *a1 = nullptr, const T *a2 = nullptr)
 {
     constexpr int NOH = (NO + 1) / 2;
-    static_assert(E0 * E1 * E2 / (AX == 0 ? E0 : AX == 1 ? E1 : E2) <= NT2, "one line per lane");
-    if (half == 0) contract<AX, E0, E1, E2, NO, 1, NT2, Q, SYM, T, ADD2, 0, OM>(src, dst, MF, lane, a1, a2);
-    else contract<AX, E0, E1, E2, NO, 1, NT2, Q, SYM, T, ADD2, OM, NOH>(src, dst, MF, lane, a1, a2);
+    static_assert(G * (E0 * E1 * E2 / (AX == 0 ? E0 : AX == 1 ? E1 : E2)) <= NT2, "one line per lane");
+    if (half == 0) contract<AX, E0, E1, E2, NO, G, NT2, Q, SYM, T, ADD2, 0, OM>(src, dst, MF, lane, a1, a2);
+    else contract<AX, E0, E1, E2, NO, G, NT2, Q, SYM, T, ADD2, OM, NOH>(src, dst, MF, lane, a1, a2);
 }
 
 // ---------------------------------------------------------------------------
@@ -701,22 +701,22 @@ k_apply(const T *__restrict__ bas, const int nex, const int ney, const int nvec,
             if constexpr (SPLIT) {
                 // nodes (s0) -> points (s3), ping-ponging between s0 and s3
                 if constexpr (!COLLOC) {
-                    contract_halves<0, P, P, P, Q, NT2, Q, 1>(s0, s3, bas + basis_bf(P, Q), half, lane);
+                    contract_halves<0, P, P, P, Q, G, NT2, Q, 1>(s0, s3, bas + basis_bf(P, Q), half, lane);
                     group_sync<NT>();
-                    contract_halves<1, Q, P, P, Q, NT2, Q, 1>(s3, s0, bas + basis_bf(P, Q), half, lane);
+                    contract_halves<1, Q, P, P, Q, G, NT2, Q, 1>(s3, s0, bas + basis_bf(P, Q), half, lane);
                     group_sync<NT>();
-                    contract_halves<2, Q, Q, P, Q, NT2, Q, 1>(s0, s3, bas + basis_bf(P, Q), half, lane);
+                    contract_halves<2, Q, Q, P, Q, G, NT2, Q, 1>(s0, s3, bas + basis_bf(P, Q), half, lane);
                     group_sync<NT>();
                 }
                 // gradient of s3: d/dr -> s1 and the first d/dt rows -> s0 (half 0), d/ds -> s2 and the
                 // other d/dt rows (half 1)
                 constexpr int NQH = (Q + 1) / 2;
                 if (half == 0) {
-                    contract<0, Q, Q, Q, Q, 1, NT2, Q, -1>(s3, s1, bas + basis_df(P, Q), lane);
-                    contract<2, Q, Q, Q, Q, 1, NT2, Q, -1, T, false, 0, NQH / 2>(s3, s0, bas + basis_df(P, Q), lane);
+                    contract<0, Q, Q, Q, Q, G, NT2, Q, -1>(s3, s1, bas + basis_df(P, Q), lane);
+                    contract<2, Q, Q, Q, Q, G, NT2, Q, -1, T, false, 0, NQH / 2>(s3, s0, bas + basis_df(P, Q), lane);
                 } else {
-                    contract<1, Q, Q, Q, Q, 1, NT2, Q, -1>(s3, s2, bas + basis_df(P, Q), lane);
-                    contract<2, Q, Q, Q, Q, 1, NT2, Q, -1, T, false, NQH / 2, NQH>(s3, s0, bas + basis_df(P, Q),
+                    contract<1, Q, Q, Q, Q, G, NT2, Q, -1>(s3, s2, bas + basis_df(P, Q), lane);
+                    contract<2, Q, Q, Q, Q, G, NT2, Q, -1, T, false, NQH / 2, NQH>(s3, s0, bas + basis_df(P, Q),
                                                                                      lane);
                 }
                 group_sync<NT>();
@@ -779,10 +779,10 @@ k_apply(const T *__restrict__ bas, const int nex, const int ney, const int nvec,
                 if constexpr (SPLIT) {
                     // transposed gradient: x lines of s1 (half 0) and y lines of s2 (half 1) in place,
                     // then the z lines of s3 with both added, into s0, shared by the halves
-                    if (half == 0) contract<0, Q, Q, Q, Q, 1, NT2, Q, -1>(s1, s1, bas + basis_dtf(P, Q), lane);
-                    else contract<1, Q, Q, Q, Q, 1, NT2, Q, -1>(s2, s2, bas + basis_dtf(P, Q), lane);
+                    if (half == 0) contract<0, Q, Q, Q, Q, G, NT2, Q, -1>(s1, s1, bas + basis_dtf(P, Q), lane);
+                    else contract<1, Q, Q, Q, Q, G, NT2, Q, -1>(s2, s2, bas + basis_dtf(P, Q), lane);
                     group_sync<NT>();
-                    contract_halves<2, Q, Q, Q, Q, NT2, Q, -1, T, true>(s3, s0, bas + basis_dtf(P, Q), half, lane,
+                    contract_halves<2, Q, Q, Q, Q, G, NT2, Q, -1, T, true>(s3, s0, bas + basis_dtf(P, Q), half, lane,
                                                                           s1, s2);
                     if constexpr (!COLLOC) group_sync<NT>();
                 } else {
@@ -813,11 +813,11 @@ k_apply(const T *__restrict__ bas, const int nex, const int ney, const int nvec,
         T *sout = s0;
         if constexpr (!COLLOC) {
             if constexpr (SPLIT) {
-                contract_halves<2, Q, Q, Q, P, NT2, Q, 1>(s0, s3, bas + basis_btf(P, Q), half, lane);
+                contract_halves<2, Q, Q, Q, P, G, NT2, Q, 1>(s0, s3, bas + basis_btf(P, Q), half, lane);
                 group_sync<NT>();
-                contract_halves<1, Q, Q, P, P, NT2, Q, 1>(s3, s0, bas + basis_btf(P, Q), half, lane);
+                contract_halves<1, Q, Q, P, P, G, NT2, Q, 1>(s3, s0, bas + basis_btf(P, Q), half, lane);
                 group_sync<NT>();
-                contract_halves<0, Q, P, P, P, NT2, Q, 1>(s0, s3, bas + basis_btf(P, Q), half, lane);
+                contract_halves<0, Q, P, P, P, G, NT2, Q, 1>(s0, s3, bas + basis_btf(P, Q), half, lane);
                 sout = s3;
             } else {
                 contract<2, Q, Q, Q, P, GV, NT, Q, 1>(s0, s0, bas + basis_btf(P, Q), tid);

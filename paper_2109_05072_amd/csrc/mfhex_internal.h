@@ -99,9 +99,9 @@ struct KgradLaunch {
 constexpr int lds_pitch(int Q) { return (Q % 2 == 0 && Q != 10) ? Q + 1 : Q; }
 constexpr int lds_buf(int Q) { return lds_pitch(Q) * Q * Q; }
 constexpr int apply_nbuf(int mode, bool split = false) { return mode == 1 ? (split ? 4 : 3) : 1; }
-// Split stages of the diffusion kernel: with one element and one vector per
-// group of NT >= 256 threads whose widest contraction (Q^2 lines) fits in half
-// the group, the two halves (two wavefronts each) share every contraction:
+// Split stages of the diffusion kernel: with G elements and one vector per
+// group of NT >= 256 threads whose widest contraction (G Q^2 lines) fits in
+// half the group, the two halves (two wavefronts each) share every contraction:
 // each takes half of the output rows, and independent contractions run side
 // by side, so no wavefront of the group sits out a contraction stage.  A
 // fourth LDS array lets every such stage write a different array than it
@@ -109,7 +109,7 @@ constexpr int apply_nbuf(int mode, bool split = false) { return mode == 1 ? (spl
 // threads the extra registers cost one wave per SIMD and 6% at q = 8.)
 constexpr bool split_stages(int Q, int mode, int G, int NT, int VC)
 {
-    return mode == 1 && G == 1 && VC == 1 && NT >= 256 && 2 * Q * Q <= NT;
+    return mode == 1 && VC == 1 && NT >= 256 && 2 * G * Q * Q <= NT;
 }
 
 // Launch variants of the fused kernels for q points per direction: G
@@ -140,14 +140,14 @@ constexpr int kNumVariants = 17;
 // faster than the best prefetching variant, q = 10 11%.
 constexpr int kVarG[9][5] = {
     {16, 8, 32, 16, 32}, {8, 4, 16, 8, 16}, {4, 2, 8, 4, 8}, {4, 2, 8, 2, 8}, {1, 2, 1, 2, 7},
-    {1, 2, 1, 1, 5},     {1, 1, 1, 2, 1},   {2, 1, 1, 1, 1}, {1, 1, 1, 1, 2}};
+    {1, 2, 1, 2, 5},     {1, 1, 1, 2, 1},   {2, 1, 1, 1, 1}, {1, 1, 1, 1, 2}};
 constexpr int kVarNT[9][5] = {
     {64, 64, 64, 128, 128},  {64, 64, 64, 128, 128},  {64, 64, 64, 128, 128},
     {128, 64, 128, 128, 256}, {64, 64, 128, 128, 256}, {64, 128, 64, 256, 256},
     {128, 256, 64, 128, 128}, {256, 128, 128, 256, 256}, {256, 128, 128, 256, 256}};
 // points per factor-load batch in the pointwise stage (0: factors prefetched at the group start)
 constexpr int kVarLate[9][5] = {{0, 0, 0, 0, 0}, {0, 0, 0, 0, 0}, {0, 0, 0, 0, 0}, {0, 0, 0, 0, 0}, {0, 0, 0, 0, 0},
-                                {0, 0, 2, 0, 0}, {0, 0, 0, 0, 2}, {0, 0, 2, 0, 2}, {0, 0, 4, 2, 0}};
+                                {0, 0, 2, 2, 0}, {0, 0, 0, 0, 2}, {0, 0, 2, 0, 2}, {0, 0, 4, 2, 0}};
 constexpr int variant_late(int Q, int v) { return v < 5 ? kVarLate[Q - 2][v] : 0; }
 constexpr bool variant_mx(int v) { return v >= 15; }
 constexpr int variant_vc(int v)
