@@ -297,7 +297,7 @@ def main():
 # (q, variant) -> points per factor-load batch of the launch variants that load the geometric
 # factors in the pointwise stage (kVarLate in csrc/mfhex_internal.h), so that the dominant kernel
 # is named as the profile summaries name it
-LATE_FACTOR_SLOTS = {(7, 2): 2, (7, 3): 2, (8, 4): 2, (9, 2): 2, (9, 4): 2, (10, 2): 4, (10, 3): 2}
+LATE_FACTOR_SLOTS = {(5, 2): 2, (6, 1): 2, (7, 2): 2, (7, 3): 2, (8, 1): 2, (8, 4): 2, (9, 2): 2, (9, 4): 2, (10, 2): 4, (10, 3): 2}
 
 
 def measure_copy_gbs(nbytes: int = 1 << 30, reps: int = 5) -> float:
