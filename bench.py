@@ -231,7 +231,9 @@ def main():
         gf = 9 <= lg["variant"] <= 14
         kname = "k_apply_gf" if gf else "k_apply"
         late = LATE_FACTOR_SLOTS.get((dom["p"] + 2, lg["variant"]))
-        suffix = " late-factors" if lg["variant"] == 14 else f" late{late}" if late and not args.otf else ""
+        pre = PREFETCH_SLOTS.get((dom["p"] + 2, lg["variant"]))
+        suffix = (" late-factors" if lg["variant"] == 14 else
+                  f" late{late}{f' pre{pre}' if pre else ''}" if late and not args.otf else "")
         dom_name = (f"{kname} p={dom['p']} q={dom['p'] + 2} diffusion {tag}double G={lg['elements_per_group']} "
                     f"NT={lg['threads_per_group']}{suffix}")
     else:
@@ -297,7 +299,9 @@ def main():
 # (q, variant) -> points per factor-load batch of the launch variants that load the geometric
 # factors in the pointwise stage (kVarLate in csrc/mfhex_internal.h), so that the dominant kernel
 # is named as the profile summaries name it
-LATE_FACTOR_SLOTS = {(5, 2): 2, (6, 1): 2, (7, 2): 2, (7, 3): 2, (8, 1): 2, (8, 4): 2, (9, 2): 2, (9, 4): 2, (10, 2): 4, (10, 3): 2}
+LATE_FACTOR_SLOTS = {(5, 2): 2, (6, 1): 2, (7, 2): 3, (7, 3): 2, (8, 1): 2, (8, 4): 2, (9, 2): 2, (9, 4): 2, (10, 2): 4, (10, 3): 2}
+# of those, (q, variant) -> points per lane still prefetched at the group start (kVarPre)
+PREFETCH_SLOTS = {(7, 2): 3, (8, 4): 2}
 
 
 def measure_copy_gbs(nbytes: int = 1 << 30, reps: int = 5) -> float:

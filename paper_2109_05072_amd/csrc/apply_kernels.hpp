@@ -32,6 +32,8 @@
 // interpolate back.
 #pragma once
 
+#include <type_traits>
+
 #include "diag_kernels.hpp"
 #include "geom.hpp"
 #include "mfhex_internal.h"
@@ -552,7 +554,7 @@ __device__ __forceinline__ void contract_halves(const T *src, T *dst, const T *_
 // registers (the same expressions as the set-up kernel), instead of reading
 // six factors per point from HBM.
 template <int P, int Q, bool COLLOC, int MODE, bool VARK, typename T, int G, int NT, int VC, bool OTF, bool DET,
-          bool STAGE = false, int LATE = 0, bool MX = false>
+          bool STAGE = false, int LATE = 0, bool MX = false, int PRE = 0>
 __global__ void __launch_bounds__(NT)
 k_apply(const T *__restrict__ bas, const int nex, const int ney, const int nvec, const int32_t *__restrict__ offsets,
         const T *__restrict__ qdata, const double *__restrict__ kappa, const double *__restrict__ wdet,
@@ -622,13 +624,16 @@ k_apply(const T *__restrict__ bas, const int nex, const int ney, const int nvec,
     // first, so their HBM latency overlaps the gather and the forward
     // contractions, and every chunk of vectors reuses them (LATE > 0: loaded in
     // the pointwise stage instead, LATE points at a time, which keeps their
-    // registers free through the contractions).
+    // registers free through the contractions; with PRE > 0 the lane's first PRE points are still
+    // prefetched and only the rest load late).
     static_assert(LATE == 0 || (VC == 1 && !OTF && MODE == kDiff), "late factor loads: one-vector diffusion");
-    constexpr int NQD = MODE == kDiff && !OTF && LATE == 0 ? kQdDiff : 0;
-    T qv[RQ][NQD > 0 ? NQD : 1];
+    static_assert(PRE == 0 || (LATE > 0 && PRE < RQ), "partial prefetch: some points late");
+    constexpr int NQD = MODE == kDiff && !OTF && (LATE == 0 || PRE > 0) ? kQdDiff : 0;
+    constexpr int KP = LATE == 0 ? RQ : PRE;  // points whose factors are prefetched
+    T qv[KP > 0 ? KP : 1][NQD > 0 ? NQD : 1];
     if constexpr (NQD > 0) {
 #pragma unroll
-        for (int k = 0; k < RQ; ++k) {
+        for (int k = 0; k < KP; ++k) {
             const int id = tid + k * NT < NPT ? tid + k * NT : NPT - 1;
             const int g = id / Q3, pt = id - g * Q3;
             // elements past the end of the row read the first element's data (and scatter nothing)
@@ -734,16 +739,18 @@ k_apply(const T *__restrict__ bas, const int nex, const int ney, const int nvec,
             {
                 // split stages write d/dt's factor product to s3 (s0 is the transposed gradient's output)
                 T *const st = SPLIT ? s3 : s0;
-#pragma unroll(LATE > 0 ? LATE : RQ)
-                for (int k = 0; k < RQ; ++k) {
+                // one point: prefetched factors (LT = false) or factors loaded here (LT = true)
+                auto point = [&](int k, auto late_tag) {
+                    constexpr bool LT = decltype(late_tag)::value;
                     const int id = tid + k * NT;
                     if (id < NPT) {
                         const int g = id / Q3, pt = id - g * Q3;
                         const int a = pt % Q, b = (pt / Q) % Q, c = pt / Q2;
                         const int loc = a + L::PITCH * b + L::PLANE * c;
-                        const T *gm = qv[LATE > 0 ? 0 : k];
+                        const T *gm = qv[0];
+                        if constexpr (!LT && NQD > 0) gm = qv[k];
                         T gl[kQdDiff];
-                        if constexpr (LATE > 0) {
+                        if constexpr (LT) {
                             const int64_t e = g < nvalid ? e0 + g : e0;
                             const T *qd = qdata + e * (kQdDiff * Q3) + pt;
 #pragma unroll
@@ -774,6 +781,15 @@ k_apply(const T *__restrict__ bas, const int nex, const int ney, const int nvec,
                             st[ls] = gm[4] * ur + gm[3] * us + gm[2] * ut;
                         }
                     }
+                };
+                if constexpr (LATE == 0) {
+#pragma unroll
+                    for (int k = 0; k < RQ; ++k) point(k, std::false_type{});
+                } else {
+#pragma unroll
+                    for (int k = 0; k < PRE; ++k) point(k, std::false_type{});
+#pragma unroll(LATE > 0 ? LATE : 1)
+                    for (int k = PRE; k < RQ; ++k) point(k, std::true_type{});
                 }
                 group_sync<NT>();
                 if constexpr (SPLIT) {
@@ -1444,7 +1460,8 @@ static hipError_t launch_apply_v(const ApplyLaunch &a)
             }
         }
         constexpr int LATE = MODE == kDiff && VC == 1 && !OTF ? variant_late(Q, V) : 0;
-        return go(k_apply<P, Q, COLLOC, MODE, VARK, T, G, NT, VC, OTF, DET, false, LATE, MX>, lds);
+        constexpr int PRE = LATE > 0 ? variant_pre(Q, V) : 0;
+        return go(k_apply<P, Q, COLLOC, MODE, VARK, T, G, NT, VC, OTF, DET, false, LATE, MX, PRE>, lds);
     }
 }
 

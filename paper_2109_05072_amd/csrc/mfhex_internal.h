@@ -147,8 +147,12 @@ constexpr int kVarNT[9][5] = {
     {128, 256, 64, 128, 128}, {256, 128, 128, 256, 256}, {256, 128, 128, 256, 256}};
 // points per factor-load batch in the pointwise stage (0: factors prefetched at the group start)
 constexpr int kVarLate[9][5] = {{0, 0, 0, 0, 0}, {0, 0, 0, 0, 0}, {0, 0, 0, 0, 0}, {0, 0, 2, 0, 0}, {0, 2, 0, 0, 0},
-                                {0, 0, 2, 2, 0}, {0, 2, 0, 0, 2}, {0, 0, 2, 0, 2}, {0, 0, 4, 2, 0}};
+                                {0, 0, 3, 2, 0}, {0, 2, 0, 0, 2}, {0, 0, 2, 0, 2}, {0, 0, 4, 2, 0}};
 constexpr int variant_late(int Q, int v) { return v < 5 ? kVarLate[Q - 2][v] : 0; }
+// of those, points per lane whose factors are still prefetched at the group start (the rest load late)
+constexpr int kVarPre[9][5] = {{0, 0, 0, 0, 0}, {0, 0, 0, 0, 0}, {0, 0, 0, 0, 0}, {0, 0, 0, 0, 0}, {0, 0, 0, 0, 0},
+                               {0, 0, 3, 0, 0}, {0, 0, 0, 0, 2}, {0, 0, 0, 0, 0}, {0, 0, 0, 0, 0}};
+constexpr int variant_pre(int Q, int v) { return v < 5 ? kVarPre[Q - 2][v] : 0; }
 constexpr bool variant_mx(int v) { return v >= 15; }
 constexpr int variant_vc(int v)
 {

@@ -40,15 +40,17 @@ def kernel_source_hash(sources=KERNEL_SOURCES) -> str:
 
 def _short(name: str) -> str:
     m = re.match(r"void mfhex::k_apply<(\d+), (\d+), (\w+), (\d), (\w+), (\w+), (\d+), (\d+)(?:, (\d+))?"
-                 r"(?:, (true|false))?(?:, (true|false))?(?:, (true|false))?(?:, (\d+))?(?:, (true|false))?>", name)
+                 r"(?:, (true|false))?(?:, (true|false))?(?:, (true|false))?(?:, (\d+))?(?:, (true|false))?"
+                 r"(?:, (\d+))?>", name)
     if m:
-        P, Q, colloc, mode, vark, T, G, NT, VC, otf, det, stage, late, mx = m.groups()
+        P, Q, colloc, mode, vark, T, G, NT, VC, otf, det, stage, late, mx, pre = m.groups()
         kind = {"0": "mass", "1": "diffusion", "2": "rhs"}[mode]
         vc = f" VC={VC}" if VC and VC != "1" else ""
         geo = " otf" if otf == "true" else ""
         dt = " det" if det == "true" else ""
         st = " staged" if stage == "true" else ""
         lt = f" late{late}" if late and late != "0" else ""
+        lt += f" pre{pre}" if pre and pre != "0" else ""
         mc = " mfma" if mx == "true" else ""
         return (f"k_apply p={int(P) - 1} q={Q} {kind}{' kappa' if vark == 'true' else ''}{geo} {T} G={G} NT={NT}"
                 f"{vc}{dt}{st}{lt}{mc}")

@@ -12,8 +12,9 @@ def test_late_factor_slots_match_the_launch_tables():
     # batch of each launch variant; it must agree with the table the kernels are instantiated from
     import bench
     src = open(os.path.join(ROOT, "paper_2109_05072_amd", "csrc", "mfhex_internal.h")).read()
-    body = re.search(r"kVarLate\[9\]\[5\]\s*=\s*\{(.*?)\};", src, re.S).group(1)
-    rows = [[int(v) for v in r.split(",")] for r in re.findall(r"\{([^{}]*)\}", body)]
-    assert len(rows) == 9 and all(len(r) == 5 for r in rows)
-    table = {(i + 2, v): n for i, r in enumerate(rows) for v, n in enumerate(r) if n}
-    assert table == bench.LATE_FACTOR_SLOTS
+    for name, mirror in (("kVarLate", bench.LATE_FACTOR_SLOTS), ("kVarPre", bench.PREFETCH_SLOTS)):
+        body = re.search(name + r"\[9\]\[5\]\s*=\s*\{(.*?)\};", src, re.S).group(1)
+        rows = [[int(v) for v in r.split(",")] for r in re.findall(r"\{([^{}]*)\}", body)]
+        assert len(rows) == 9 and all(len(r) == 5 for r in rows)
+        table = {(i + 2, v): n for i, r in enumerate(rows) for v, n in enumerate(r) if n}
+        assert table == mirror, name
