@@ -299,9 +299,9 @@ def main():
 # (q, variant) -> points per factor-load batch of the launch variants that load the geometric
 # factors in the pointwise stage (kVarLate in csrc/mfhex_internal.h), so that the dominant kernel
 # is named as the profile summaries name it
-LATE_FACTOR_SLOTS = {(5, 2): 2, (6, 1): 2, (7, 2): 3, (7, 3): 2, (8, 1): 2, (8, 4): 2, (9, 2): 2, (9, 4): 2, (10, 2): 4, (10, 3): 2}
+LATE_FACTOR_SLOTS = {(5, 2): 2, (6, 1): 2, (7, 2): 3, (7, 3): 3, (8, 1): 2, (8, 4): 2, (9, 2): 2, (9, 4): 2, (10, 2): 4, (10, 3): 2}
 # of those, (q, variant) -> points per lane still prefetched at the group start (kVarPre)
-PREFETCH_SLOTS = {(7, 2): 3, (8, 4): 2}
+PREFETCH_SLOTS = {(7, 2): 3, (7, 3): 3, (8, 4): 2}
 
 
 def measure_copy_gbs(nbytes: int = 1 << 30, reps: int = 5) -> float:

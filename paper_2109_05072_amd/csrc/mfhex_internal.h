@@ -140,18 +140,18 @@ constexpr int kNumVariants = 17;
 // faster than the best prefetching variant, q = 10 11%.
 constexpr int kVarG[9][5] = {
     {16, 8, 32, 16, 32}, {8, 4, 16, 8, 16}, {4, 2, 8, 4, 8}, {4, 2, 5, 2, 8}, {1, 3, 1, 2, 7},
-    {1, 2, 1, 2, 5},     {1, 2, 1, 2, 1},   {2, 1, 1, 1, 1}, {1, 1, 1, 1, 2}};
+    {1, 2, 1, 4, 5},     {1, 2, 1, 2, 1},   {2, 1, 1, 1, 1}, {1, 1, 1, 1, 2}};
 constexpr int kVarNT[9][5] = {
     {64, 64, 64, 128, 128},  {64, 64, 64, 128, 128},  {64, 64, 64, 128, 128},
     {128, 64, 256, 128, 256}, {64, 256, 128, 128, 256}, {64, 128, 64, 256, 256},
     {128, 256, 64, 128, 128}, {256, 128, 128, 256, 256}, {256, 128, 128, 256, 256}};
 // points per factor-load batch in the pointwise stage (0: factors prefetched at the group start)
 constexpr int kVarLate[9][5] = {{0, 0, 0, 0, 0}, {0, 0, 0, 0, 0}, {0, 0, 0, 0, 0}, {0, 0, 2, 0, 0}, {0, 2, 0, 0, 0},
-                                {0, 0, 3, 2, 0}, {0, 2, 0, 0, 2}, {0, 0, 2, 0, 2}, {0, 0, 4, 2, 0}};
+                                {0, 0, 3, 3, 0}, {0, 2, 0, 0, 2}, {0, 0, 2, 0, 2}, {0, 0, 4, 2, 0}};
 constexpr int variant_late(int Q, int v) { return v < 5 ? kVarLate[Q - 2][v] : 0; }
 // of those, points per lane whose factors are still prefetched at the group start (the rest load late)
 constexpr int kVarPre[9][5] = {{0, 0, 0, 0, 0}, {0, 0, 0, 0, 0}, {0, 0, 0, 0, 0}, {0, 0, 0, 0, 0}, {0, 0, 0, 0, 0},
-                               {0, 0, 3, 0, 0}, {0, 0, 0, 0, 2}, {0, 0, 0, 0, 0}, {0, 0, 0, 0, 0}};
+                               {0, 0, 3, 3, 0}, {0, 0, 0, 0, 2}, {0, 0, 0, 0, 0}, {0, 0, 0, 0, 0}};
 constexpr int variant_pre(int Q, int v) { return v < 5 ? kVarPre[Q - 2][v] : 0; }
 constexpr bool variant_mx(int v) { return v >= 15; }
 constexpr int variant_vc(int v)
