@@ -130,6 +130,8 @@ def main():
     ap.add_argument("--sweep", action="store_true", help="report the time of every launch variant (stderr)")
     ap.add_argument("--interleaved", action="store_true",
                     help="time the steps one by one (one apply of every order per step) instead of order by order")
+    ap.add_argument("--fp64-rate", action="store_true",
+                    help="only measure the FP64 pipes: 16x16x4 and 4x4x4 matrix-core and vector FMA chains")
     ap.add_argument("--calib-copy", action="store_true",
                     help="after timing, copy 1 GiB device-to-device twice (a kernel of known traffic, "
                          "used to scale the HBM byte counters)")
@@ -145,6 +147,9 @@ def main():
     import paper_2109_05072_amd as mf
 
     torch.cuda.set_device(0)
+    if args.fp64_rate:
+        print(json.dumps({"fp64_rate": fp64_rates(), "peak_tflops": FP64_PEAK_TFLOPS}), flush=True)
+        return
     if args.batched_config:
         print(json.dumps(batched_one([int(v) for v in args.batched_config.split(",")], args.steps, args.warmup)),
               flush=True)
@@ -321,6 +326,48 @@ def measure_copy_gbs(nbytes: int = 1 << 30, reps: int = 5) -> float:
     del a, b
     torch.cuda.empty_cache()
     return 2 * nbytes / float(np.median(ts)) / 1e9
+
+
+def fp64_rates(nblocks: int = 2048, iters: int = 4096, reps: int = 3) -> list:
+    """FP64 throughput of the matrix-core and vector pipes (libhbmprobe.so: chains of 16x16x4 and
+    4x4x4 FP64 MFMA and of v_fma_f64 with independent accumulators, registers only), median of reps
+    event-timed launches of nblocks x 256 threads."""
+    import ctypes as C
+    import torch
+    from paper_2109_05072_amd import build as libbuild
+    if not os.path.exists(libbuild.PROBE_LIB):
+        raise RuntimeError(f"{libbuild.PROBE_LIB} is not built (run __graft_entry__.build())")
+    lib = C.CDLL(libbuild.PROBE_LIB)
+    lib.fp64_rate.argtypes = [C.c_int, C.c_void_p, C.c_int, C.c_int, C.c_void_p]
+    lib.fp64_rate.restype = C.c_int
+    lib.fp64_rate_flops_per_wave_iter.argtypes = [C.c_int]
+    lib.fp64_rate_flops_per_wave_iter.restype = C.c_double
+    out = torch.empty(nblocks * 256, dtype=torch.float64, device="cuda")
+    stream = torch.cuda.current_stream().cuda_stream
+    res = []
+    for kind, name in ((0, "mfma_f64_16x16x4"), (1, "mfma_f64_4x4x4_4blocks"), (2, "v_fma_f64")):
+        def run():
+            rc = lib.fp64_rate(kind, out.data_ptr(), nblocks, iters, stream)
+            if rc != 0:
+                raise RuntimeError(f"fp64_rate({kind}) failed: {rc}")
+        run()
+        ts = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            run()
+            e1.record()
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1) / 1e3)
+        t = float(np.median(ts))
+        flops = nblocks * 256 / 64 * iters * lib.fp64_rate_flops_per_wave_iter(kind)
+        res.append({"kind": name, "ms": round(t * 1e3, 4), "tflops": round(flops / t / 1e12, 2),
+                    "frac_of_peak": round(flops / t / 1e12 / FP64_PEAK_TFLOPS, 4)})
+    if not bool(torch.isfinite(out).all()):
+        raise RuntimeError("fp64 rate probe produced non-finite results")
+    del out
+    torch.cuda.empty_cache()
+    return res
 
 
 def hbm_ceiling(nbytes: int = 4 << 30, reps: int = 5) -> dict:

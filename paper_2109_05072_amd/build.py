@@ -59,19 +59,20 @@ def build(verbose: bool = False, jobs: int | None = None) -> str:
     return LIB
 
 
-PROBE_SRC = os.path.join(HERE, "probe", "hbm_stream.hip")
+PROBE_SRCS = [os.path.join(HERE, "probe", "hbm_stream.hip"), os.path.join(HERE, "probe", "fp64_rate.hip")]
 PROBE_LIB = os.path.join(HERE, "libhbmprobe.so")
 
 
 def build_probe(verbose: bool = False) -> str:
-    """The HBM streaming probe (read / copy / fill kernels) the benchmark times next to the operator."""
+    """The measuring kernels the benchmark times next to the operator: HBM streaming (read / copy /
+    fill) and FP64 pipe throughput (matrix-core and vector FMA chains)."""
     tmp = PROBE_LIB + ".tmp"
-    cmd = [HIPCC] + FLAGS + ["-shared", PROBE_SRC, "-o", tmp]
+    cmd = [HIPCC] + FLAGS + ["-shared"] + PROBE_SRCS + ["-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
-        raise RuntimeError(f"hipcc failed on {PROBE_SRC}:\n{r.stdout}\n{r.stderr}")
+        raise RuntimeError(f"hipcc failed on {PROBE_SRCS}:\n{r.stdout}\n{r.stderr}")
     os.replace(tmp, PROBE_LIB)
     return PROBE_LIB
 

@@ -2,7 +2,8 @@
 
 ``python -m paper_2109_05072_amd.prof_summary trace <dir> <command...>``
     kernel-trace statistics (``*_kernel_stats.csv``) -> text table
-    (``trace-tet``: the same, hashed over the tetrahedral kernel sources).
+    (``trace-tet``, ``trace-probe``: the same, hashed over the tetrahedral kernel sources or the
+    measuring kernels).
 ``python -m paper_2109_05072_amd.prof_summary traffic <fetch_dir> <write_dir> <command...>``
     FETCH_SIZE / WRITE_SIZE per dispatch of each apply kernel, scaled by what
     the same counters read for the 1 GiB device-to-device copy that
@@ -27,6 +28,7 @@ from collections import defaultdict
 HERE = os.path.dirname(os.path.abspath(__file__))
 KERNEL_SOURCES = ("csrc/apply_kernels.hpp", "csrc/mfhex_internal.h", "csrc/geom.hpp", "csrc/diag_kernels.hpp")
 TET_SOURCES = ("csrc/tet_kernels.hip", "csrc/tet.h")
+PROBE_SOURCES = ("probe/hbm_stream.hip", "probe/fp64_rate.hip")
 COPY_BYTES = 1 << 30
 
 
@@ -242,6 +244,8 @@ if __name__ == "__main__":
         sys.stdout.write(trace_summary(sys.argv[2], " ".join(sys.argv[3:])))
     elif mode == "trace-tet":
         sys.stdout.write(trace_summary(sys.argv[2], " ".join(sys.argv[3:]), TET_SOURCES))
+    elif mode == "trace-probe":
+        sys.stdout.write(trace_summary(sys.argv[2], " ".join(sys.argv[3:]), PROBE_SOURCES))
     elif mode == "counters":
         # counters <dir1,dir2,...> <cmd...>
         sys.stdout.write(counter_summary(sys.argv[2].split(","), " ".join(sys.argv[3:])))

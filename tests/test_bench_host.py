@@ -18,3 +18,18 @@ def test_late_factor_slots_match_the_launch_tables():
         assert len(rows) == 9 and all(len(r) == 5 for r in rows)
         table = {(i + 2, v): n for i, r in enumerate(rows) for v, n in enumerate(r) if n}
         assert table == mirror, name
+
+
+def test_measuring_library_exports():
+    # the benchmark's measuring kernels (HBM streaming, FP64 pipe rates) load and export their entry points
+    import ctypes
+    from paper_2109_05072_amd import build as libbuild
+    if not os.path.exists(libbuild.PROBE_LIB):
+        import pytest
+        pytest.skip("libhbmprobe.so not built")
+    lib = ctypes.CDLL(libbuild.PROBE_LIB)
+    for name in ("hbm_stream", "fp64_rate", "fp64_rate_flops_per_wave_iter"):
+        assert hasattr(lib, name), name
+    f = lib.fp64_rate_flops_per_wave_iter
+    f.argtypes, f.restype = [ctypes.c_int], ctypes.c_double
+    assert [f(k) for k in range(3)] == [4 * 2 * 16 * 16 * 4, 4 * 2 * 4 * 4 * 4 * 4, 8 * 2 * 64]
